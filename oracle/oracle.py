@@ -1,0 +1,364 @@
+"""DartMinHash CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The product path (the HIP library and its
+binding) never touches it.
+
+Layout:
+
+* constants of the method, derived here from their mathematical definitions
+  with exact arithmetic (``fractions``/``decimal``) and IEEE binary64 division;
+* a ctypes wrapper around ``dms_oracle.c`` (the single-threaded DartHash,
+  DartMinHash and LSH loops);
+* the two estimators and the Hamming top-k scan, written directly with numpy.
+
+Paper references are to Christiani, "DartMinHash: Fast Sketching for Weighted
+Sets" (arXiv 2005.11547).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from decimal import Decimal, getcontext
+from fractions import Fraction
+from functools import lru_cache
+from math import factorial
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dms_oracle.c")
+LIB = os.path.join(HERE, "libdms_oracle.so")
+
+TABLE = 300
+NPOIS = 20
+STATUS = {"ok": 0, "empty": 1, "range": 2, "invalid": 3}
+SCHED_PLUS_ONE = 0   # phi = 1, 2, 3, ... (proof of Theorem 1)
+SCHED_DOUBLE = 1     # phi = phi0, 2 phi0, 4 phi0, ...
+MASK64 = (1 << 64) - 1
+
+
+# --------------------------------------------------------------------------
+# Constants
+# --------------------------------------------------------------------------
+def t_of_k(k: int) -> int:
+    """t = ceil(k ln k) + k (proof of Theorem 1), with a 60-digit logarithm."""
+    if k < 1:
+        raise ValueError("k must be positive")
+    getcontext().prec = 60
+    v = Decimal(k) * Decimal(k).ln()
+    c = int(v.to_integral_value(rounding="ROUND_CEILING"))
+    return c + k
+
+
+@lru_cache(maxsize=None)
+def poisson_thresholds() -> tuple:
+    """C[n] = floor(2^64 * P[Poisson(1) <= n]) for n = 0..19, exactly.
+
+    P[Poi(1) <= n] = e^-1 * sum_{m<=n} 1/m!.  e^-1 is bracketed by two partial
+    sums of its alternating series; the floor must agree at both ends.
+    """
+    lo = sum(Fraction((-1) ** m, factorial(m)) for m in range(0, 42))  # odd last term: below
+    hi = sum(Fraction((-1) ** m, factorial(m)) for m in range(0, 41))  # even last term: above
+    assert lo < hi
+    out = []
+    for n in range(NPOIS):
+        s = sum(Fraction(1, factorial(m)) for m in range(n + 1))
+        a = (lo * s * 2 ** 64).__floor__()
+        b = (hi * s * 2 ** 64).__floor__()
+        assert a == b, n
+        out.append(int(a))
+    return tuple(out)
+
+
+def mt19937_64(seed: int, n: int) -> list[int]:
+    """First n outputs of MT19937-64 (Matsumoto and Nishimura), seeded the
+    standard way (init_genrand64)."""
+    NN, MM = 312, 156
+    MATRIX_A = 0xB5026F5AA96619E9
+    UM, LM = 0xFFFFFFFF80000000, 0x7FFFFFFF
+    mt = [0] * NN
+    mt[0] = seed & MASK64
+    for i in range(1, NN):
+        mt[i] = (6364136223846793005 * (mt[i - 1] ^ (mt[i - 1] >> 62)) + i) & MASK64
+    idx = NN
+    out = []
+    for _ in range(n):
+        if idx >= NN:
+            for i in range(NN):
+                x = (mt[i] & UM) | (mt[(i + 1) % NN] & LM)
+                xa = x >> 1
+                if x & 1:
+                    xa ^= MATRIX_A
+                mt[i] = mt[(i + MM) % NN] ^ xa
+            idx = 0
+        x = mt[idx]
+        idx += 1
+        x ^= (x >> 29) & 0x5555555555555555
+        x ^= (x << 17) & 0x71D67FFFEDA60000
+        x ^= (x << 37) & 0xFFF7EEE000000000
+        x ^= x >> 43
+        out.append(x & MASK64)
+    return out
+
+
+@lru_cache(maxsize=4096)
+def _keys(seed: int) -> tuple:
+    return tuple(mt19937_64(seed, 6))
+
+
+def hash_keys(seed: int) -> dict:
+    """The six hash keys: the first six MT19937-64 outputs for the seed."""
+    k = _keys(seed)
+    return dict(key_r=k[0], key_a=k[1], key_u=k[2], key_v=k[3], key_s=k[4], key_l=k[5])
+
+
+def tables(t: int):
+    """W[nu] = RN(RN(2^nu - 1)/t), R[rho] = RN(2^rho - 1), u = RN(1/t): the lower
+    corners of the weight and rank regions (Section 2) and the unit column width."""
+    W = [float(2 ** nu - 1) / float(t) for nu in range(TABLE)]
+    R = [float(2 ** rho - 1) for rho in range(TABLE)]
+    return W, R, 1.0 / float(t)
+
+
+# --------------------------------------------------------------------------
+# ctypes
+# --------------------------------------------------------------------------
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("key_r", ctypes.c_uint64), ("key_a", ctypes.c_uint64), ("key_u", ctypes.c_uint64),
+        ("key_v", ctypes.c_uint64), ("key_s", ctypes.c_uint64), ("key_l", ctypes.c_uint64),
+        ("pois", ctypes.c_uint64 * NPOIS),
+        ("W", ctypes.c_double * TABLE),
+        ("R", ctypes.c_double * TABLE),
+        ("u", ctypes.c_double),
+        ("t", ctypes.c_uint32),
+        ("phi0", ctypes.c_double),
+        ("schedule", ctypes.c_int32),
+        ("phi_max", ctypes.c_double),
+    ]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_int64), ("areas", ctypes.c_int64),
+                ("generated", ctypes.c_int64), ("rank_pass", ctypes.c_int64),
+                ("accepted", ctypes.c_int64)]
+
+
+DART_DTYPE = np.dtype([("i", "<u4"), ("nu", "<u2"), ("rho", "<u2"), ("w", "<u4"), ("r", "<u4"),
+                       ("j", "<u4"), ("pad", "<u4"), ("rank", "<f8"), ("weight", "<f8"),
+                       ("s", "<u8")])
+COUNTER_DTYPE = np.dtype([("regions", "<i8"), ("areas", "<i8"), ("generated", "<i8"),
+                          ("rank_pass", "<i8"), ("accepted", "<i8")])
+
+
+def build(force: bool = False) -> str:
+    """Compile dms_oracle.c with strict IEEE binary64 semantics."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fno-finite-math-only", "-mfpmath=sse", "-msse2", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.dmso_mix64.argtypes = [ctypes.c_uint64]
+        L.dmso_mix64.restype = ctypes.c_uint64
+        L.dmso_darthash.argtypes = [P(Params), ctypes.c_int64, vp, vp, ctypes.c_double, vp,
+                                    ctypes.c_int64, P(ctypes.c_int64), vp]
+        L.dmso_minhash_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp,
+                                       P(ctypes.c_double), vp]
+        L.dmso_sketch_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32,
+                                      vp, vp, vp, vp, vp, vp, vp]
+        L.dmso_lsh_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                   vp, vp, vp, vp, vp, P(ctypes.c_double)]
+        L.dmso_lsh_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32,
+                                   ctypes.c_int32, vp, vp]
+        for f in ("dmso_darthash", "dmso_minhash_set", "dmso_sketch_csr", "dmso_lsh_set",
+                  "dmso_lsh_csr"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def mix64(z: int) -> int:
+    return int(lib().dmso_mix64(z & MASK64))
+
+
+def make_params(seed: int, t: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE,
+                phi_max: float = 2.0 ** 20) -> Params:
+    p = Params()
+    for name, v in hash_keys(seed).items():
+        setattr(p, name, v)
+    for n, c in enumerate(poisson_thresholds()):
+        p.pois[n] = c
+    W, R, u = tables(t)
+    for i in range(TABLE):
+        p.W[i] = W[i]
+        p.R[i] = R[i]
+    p.u = u
+    p.t = t
+    p.phi0 = phi0
+    p.schedule = schedule
+    p.phi_max = phi_max
+    return p
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _csr(row_ptr, idx, w):
+    return (np.ascontiguousarray(row_ptr, dtype=np.int64),
+            np.ascontiguousarray(idx, dtype=np.int32),
+            np.ascontiguousarray(w, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Method
+# --------------------------------------------------------------------------
+def darthash(idx, w, tau: float, t: int, seed: int):
+    """DartHash_t(x, phi) with tau = phi/||x||_1 given explicitly (Algorithm 1).
+    Returns (status, structured array of darts, counters dict)."""
+    P = make_params(seed, t)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = ctypes.c_int64(0)
+    cnt = Counters()
+    st = lib().dmso_darthash(ctypes.byref(P), len(idx), _ptr(idx), _ptr(w), tau, None, 0,
+                             ctypes.byref(n), ctypes.byref(cnt))
+    out = np.zeros(n.value, dtype=DART_DTYPE)
+    st = lib().dmso_darthash(ctypes.byref(P), len(idx), _ptr(idx), _ptr(w), tau, _ptr(out),
+                             n.value, ctypes.byref(n), ctypes.byref(cnt))
+    return st, out, {f: getattr(cnt, f) for f, _ in Counters._fields_}
+
+
+def minhash_set(idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
+                schedule: int = SCHED_PLUS_ONE):
+    """DartMinHash of one set (Theorem 1).  Returns (status, s[k] uint64,
+    rank[k] float64, phi_final, counters)."""
+    t = t_of_k(k) if t is None else t
+    P = make_params(seed, t, phi0, schedule)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    s = np.zeros(k, dtype=np.uint64)
+    r = np.zeros(k, dtype=np.float64)
+    phi = ctypes.c_double(0.0)
+    cnt = Counters()
+    st = lib().dmso_minhash_set(ctypes.byref(P), k, len(idx), _ptr(idx), _ptr(w), _ptr(s),
+                                _ptr(r), ctypes.byref(phi), ctypes.byref(cnt))
+    return st, s, r, phi.value, {f: getattr(cnt, f) for f, _ in Counters._fields_}
+
+
+def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
+               schedule: int = SCHED_PLUS_ONE, full: bool = False):
+    """DartMinHash of every row of a CSR matrix.
+
+    Returns dict with u32 [n,k], bits [n, ceil(k/64)] (uint64), status [n] (int8),
+    and with ``full`` also s [n,k], rank [n,k], phi [n], counters [n]."""
+    t = t_of_k(k) if t is None else t
+    P = make_params(seed, t, phi0, schedule)
+    row_ptr, idx, w = _csr(row_ptr, idx, w)
+    n = len(row_ptr) - 1
+    words = (k + 63) // 64
+    u32 = np.zeros((n, k), dtype=np.uint32)
+    bits = np.zeros((n, words), dtype=np.uint64)
+    status = np.zeros(n, dtype=np.int8)
+    s = np.zeros((n, k), dtype=np.uint64) if full else None
+    rk = np.zeros((n, k), dtype=np.float64) if full else None
+    phi = np.zeros(n, dtype=np.float64) if full else None
+    cnt = np.zeros(n, dtype=COUNTER_DTYPE) if full else None
+    st = lib().dmso_sketch_csr(ctypes.byref(P), n, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
+                               _ptr(u32), _ptr(bits), _ptr(status), _ptr(s), _ptr(rk),
+                               _ptr(phi), _ptr(cnt))
+    if st != 0:
+        raise MemoryError("oracle out of memory")
+    out = dict(u32=u32, bits=bits, status=status)
+    if full:
+        out.update(s=s, rank=rk, phi=phi, counters=cnt)
+    return out
+
+
+def lsh_set(idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
+            schedule: int = SCHED_PLUS_ONE):
+    """(L,K) LSH values of one set.  Returns (status, keys[L], s[L,K], rank[L,K], phi)."""
+    P = make_params(seed, L * K, phi0, schedule)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    keys = np.zeros(L, dtype=np.uint64)
+    s = np.zeros((L, K), dtype=np.uint64)
+    r = np.zeros((L, K), dtype=np.float64)
+    phi = ctypes.c_double(0.0)
+    st = lib().dmso_lsh_set(ctypes.byref(P), L, K, len(idx), _ptr(idx), _ptr(w), _ptr(keys),
+                            _ptr(s), _ptr(r), ctypes.byref(phi))
+    return st, keys, s, r, phi.value
+
+
+def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
+            schedule: int = SCHED_PLUS_ONE):
+    P = make_params(seed, L * K, phi0, schedule)
+    row_ptr, idx, w = _csr(row_ptr, idx, w)
+    n = len(row_ptr) - 1
+    keys = np.zeros((n, L), dtype=np.uint64)
+    status = np.zeros(n, dtype=np.int8)
+    st = lib().dmso_lsh_csr(ctypes.byref(P), n, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
+                            _ptr(keys), _ptr(status))
+    if st != 0:
+        raise MemoryError("oracle out of memory")
+    return dict(keys=keys, status=status)
+
+
+# --------------------------------------------------------------------------
+# Estimators and search (Section 1.1)
+# --------------------------------------------------------------------------
+def jaccard_est_u32(a, b):
+    """J-hat = (1/k) * #{j : h_j(x) = h_j(y)} for each row pair."""
+    a = np.asarray(a, dtype=np.uint32)
+    b = np.asarray(b, dtype=np.uint32)
+    return (a == b).sum(axis=-1) / a.shape[-1]
+
+
+def popcount64(v):
+    v = np.asarray(v, dtype=np.uint64)
+    out = np.zeros(v.shape, dtype=np.int64)
+    for sh in range(0, 64, 8):
+        byte = ((v >> np.uint64(sh)) & np.uint64(0xFF)).astype(np.int64)
+        out += _POP8[byte]
+    return out
+
+
+_POP8 = np.array([bin(i).count("1") for i in range(256)], dtype=np.int64)
+
+
+def jaccard_est_1bit(a, b, k: int):
+    """1-bit sketches: each bit agrees with probability (1+J)/2, so
+    J-hat = 1 - 2 * (#disagreeing bits)/k (unclamped)."""
+    d = popcount64(np.bitwise_xor(np.asarray(a, np.uint64), np.asarray(b, np.uint64))).sum(axis=-1)
+    return 1.0 - 2.0 * d / k
+
+
+def hamming_topk(db_bits, q_bits, topk: int):
+    """For every query row, the topk database rows of smallest Hamming distance,
+    ties broken by the smaller row id.  Returns (ids [nq, topk] int64,
+    dist [nq, topk] int32)."""
+    db = np.asarray(db_bits, dtype=np.uint64)
+    q = np.asarray(q_bits, dtype=np.uint64)
+    ids = np.zeros((q.shape[0], topk), dtype=np.int64)
+    dist = np.zeros((q.shape[0], topk), dtype=np.int32)
+    for qi in range(q.shape[0]):
+        d = popcount64(np.bitwise_xor(db, q[qi][None, :])).sum(axis=1)
+        order = np.lexsort((np.arange(db.shape[0]), d))[:topk]
+        ids[qi, :len(order)] = order
+        dist[qi, :len(order)] = d[order]
+    return ids, dist
