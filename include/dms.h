@@ -1,0 +1,191 @@
+/*
+ * dms.h -- C ABI of the DartMinHash library for AMD Instinct MI355X (gfx950).
+ *
+ * Christiani, "DartMinHash: Fast Sketching for Weighted Sets" (arXiv 2005.11547).
+ *
+ * Conventions for every call:
+ *  - Weighted sets arrive as one CSR matrix: row_ptr (int64, n_sets+1 entries,
+ *    non-decreasing, row_ptr[0] = 0), idx (int32 element ids, read as uint32),
+ *    w (float64 weights).  A row lists the nonzeros of one set x in R^d_{>=0};
+ *    zero weights are skipped, as Algorithm 1 iterates over {i : x_i > 0}.
+ *  - Pointers marked "device" must be device memory of the context's GPU;
+ *    the caller allocates, owns and frees every input and output buffer.  The
+ *    context owns only its internal tables and scratch space.
+ *  - Calls are asynchronous on the context's stream (dms_set_stream); argument
+ *    errors are reported synchronously by the return value, per-set data
+ *    problems by out_status.  dms_sync waits for the stream.
+ *  - A context is not thread safe; use one per host thread.
+ *  - Return value: DMS_OK (0) or a negative DMS_E* code; dms_last_error gives
+ *    the message of the last failure on that context.
+ */
+#ifndef DMS_H
+#define DMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dms_status;
+#define DMS_OK 0
+#define DMS_EINVAL (-1) /* an argument is out of range or a pointer is NULL */
+#define DMS_EHIP (-2)   /* the HIP runtime reported an error */
+#define DMS_ENOMEM (-3) /* the context could not allocate its scratch space */
+#define DMS_ESPEC (-4)  /* a specification constant could not be derived exactly */
+
+/* Per-set status codes written to out_status arrays. */
+#define DMS_SET_OK 0      /* sketch computed */
+#define DMS_SET_EMPTY 1   /* no positive weight: the minhash is undefined (J = 0/0) */
+#define DMS_SET_RANGE 2   /* largest weight outside [2^-256, 2^256], or phi beyond its cap */
+#define DMS_SET_INVALID 3 /* a negative, NaN or infinite weight */
+
+/* Engines for the sketch and LSH calls (dms_set_option DMS_OPT_ENGINE). */
+#define DMS_ENGINE_FAST 0  /* flattened wave pipeline, work-stealing persistent grid */
+#define DMS_ENGINE_PLAIN 1 /* one wave per set, one lane per nonzero, one launch */
+
+/* Options (dms_set_option / dms_get_option).  None changes any output:
+ * Theorem 1's output is independent of the phi schedule. */
+#define DMS_OPT_ENGINE 0    /* DMS_ENGINE_* */
+#define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1) */
+#define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 2) */
+#define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
+
+/* Formats of dms_jaccard_est. */
+#define DMS_FMT_U32 0  /* k uint32 minhash values per set */
+#define DMS_FMT_1BIT 1 /* ceil(k/64) uint64 words per set, bit j at bit j%64 of word j/64 */
+
+typedef struct dms_ctx_s* dms_ctx;
+
+/* Create a context on HIP device `device`.  `seed` selects the hash functions:
+ * the six 64-bit keys are the first six outputs of MT19937-64 seeded with it
+ * (the paper seeds its hashing with a Mersenne Twister, Section 4
+ * "Implementation").  Sketches made with different seeds are not comparable.
+ * On success *out receives the context.  Errors: DMS_EINVAL (out NULL, bad
+ * device), DMS_EHIP. */
+dms_status dms_create(dms_ctx* out, int device, uint64_t seed);
+
+/* Destroy a context and free what it owns (not the caller's buffers). */
+dms_status dms_destroy(dms_ctx ctx);
+
+/* Use `hip_stream` (a hipStream_t, or NULL for the null stream) for all later
+ * calls on this context. */
+dms_status dms_set_stream(dms_ctx ctx, void* hip_stream);
+
+/* Set / read one DMS_OPT_* option.  Errors: DMS_EINVAL for an unknown option
+ * or a value outside its range (phi0 and phi_max must be positive and finite). */
+dms_status dms_set_option(dms_ctx ctx, int32_t option, double value);
+dms_status dms_get_option(dms_ctx ctx, int32_t option, double* value);
+
+/*
+ * DartMinHash (Theorem 1, Section 3; DartHash is Algorithm 1, Section 2): for
+ * every row s of the CSR matrix, k independent weighted minhashes.
+ * t = ceil(k ln k) + k darts per unit of phi are hashed to k buckets; bucket j
+ * keeps its dart of smallest rank (ties: smaller id hash); phi doubles until no
+ * bucket is empty.
+ *   row_ptr  device int64[n_sets+1]
+ *   idx      device int32[row_ptr[n_sets]]
+ *   w        device float64[row_ptr[n_sets]]
+ *   k        1 .. 4096
+ *   out_u32  device uint32[n_sets*k] or NULL: low 32 bits of bucket j's dart
+ *            id hash at [s*k + j]; 0xFFFFFFFF for a set whose status is not OK
+ *   out_bits device uint64[n_sets*ceil(k/64)] or NULL: the 1-bit sketch
+ *            (Section 1.1), bit j = bit 0 of that hash, at bit j%64 of word
+ *            s*ceil(k/64) + j/64; all zero for a set whose status is not OK
+ *   out_status device int8[n_sets] or NULL: DMS_SET_*
+ *   out_s    device uint64[n_sets*k] or NULL: the full 64-bit dart id hash
+ *   out_rank device float64[n_sets*k] or NULL: the dart's rank (+inf if not OK)
+ * Errors: DMS_EINVAL (k out of range, n_sets < 0, a required pointer NULL),
+ * DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
+                          const int32_t* idx, const double* w, int32_t k, uint32_t* out_u32,
+                          uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                          double* out_rank);
+
+/*
+ * (L,K) LSH values (Section 1.2 "Fast similarity search" and Section 3
+ * "Bottom-k minhash and fast approximate near neighbor search"): DartHash with
+ * t = L*K, darts hashed to L tables, each table's K darts of smallest rank in
+ * ascending order (a repeated dart counts once), phi doubling until every
+ * table holds K darts; table l's key folds the ordered dart id hashes:
+ * h = mix(K_L ^ l), h = mix(h ^ s_m) for m < K.  Two sets share table l's key
+ * with probability J^K, independently across tables.
+ *   L 1..1024, K 1..64, L*K <= 65536
+ *   out_keys device uint64[n_sets*L] at [s*L + l]; 0 for a set not OK
+ *   out_status device int8[n_sets] or NULL
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_lsh_keys(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                        const double* w, int32_t L, int32_t K, uint64_t* out_keys,
+                        int8_t* out_status);
+
+/*
+ * Weighted Jaccard estimates from sketches (Section 1.1): for pair p, with a
+ * and b holding n_pairs sketches each (row p of a against row p of b):
+ *   DMS_FMT_U32:  out[p] = (#j with a[p*k+j] == b[p*k+j]) / k
+ *   DMS_FMT_1BIT: out[p] = 1 - 2 * popcount((a ^ b) restricted to k bits) / k
+ *                 (each bit agrees with probability (1+J)/2; not clamped)
+ *   a, b device arrays in the format's layout; out device float64[n_pairs].
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_jaccard_est(dms_ctx ctx, int64_t n_pairs, const void* a, const void* b, int32_t k,
+                           int32_t format, double* out);
+
+/*
+ * Hamming top-k search over 1-bit sketches (the similarity-search use of
+ * Section 1.1): for every query row q, the `topk` database rows with the
+ * smallest Hamming distance, ascending by (distance, row id).
+ *   db      device uint64[n_db*words]       (1-bit sketches, `words` words each)
+ *   queries device uint64[n_q*words]
+ *   out_ids device int64[n_q*topk]   (-1 where n_db < topk)
+ *   out_dist device int32[n_q*topk]  (-1 where n_db < topk)
+ *   words 1..64, n_q 0..4096, topk 1..64, n_db < 2^31
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_hamming_topk(dms_ctx ctx, const uint64_t* db, int64_t n_db, int32_t words,
+                            const uint64_t* queries, int64_t n_q, int32_t topk, int64_t* out_ids,
+                            int32_t* out_dist);
+
+/*
+ * Measurement support (roofline calibration; not part of the sketching path).
+ * kind 0: 8 independent chains of the specification's 64-bit mixer per thread,
+ *         `iters` steps each (blocks*256 threads): the chip's hashing rate.
+ * kind 1: 8 chains of 32-bit xor/add per thread: full-rate integer issue.
+ * kind 2: copy `bytes` (multiple of 16) from device buffer a to device buffer b
+ *         with a grid-stride loop: HBM bandwidth and the reference for scaling
+ *         the FETCH_SIZE / WRITE_SIZE counters.
+ * a must hold at least 8 bytes for kinds 0 and 1.  Blocks until the kernel
+ * is done and stores its duration in *out_ms (HIP events on the context's
+ * stream).  Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_calibrate(dms_ctx ctx, int32_t kind, int32_t iters, int64_t bytes, int32_t blocks,
+                         void* a, void* b, double* out_ms);
+
+/* Wait until all work queued on the context's stream is done. */
+dms_status dms_sync(dms_ctx ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* dms_last_error(dms_ctx ctx);
+
+/* Name of a return or per-set status code. */
+const char* dms_status_str(dms_status s);
+
+/*
+ * Host-only queries of the specification (no GPU needed).
+ * dms_t_of_k: t = ceil(k ln k) + k (proof of Theorem 1).
+ * dms_spec_constants: for `seed` and t, the six hash keys (K_R, K_A, K_U, K_V,
+ * K_S, K_L), the 20 Poisson(1) thresholds floor(2^64 P[Poi(1) <= n]), the
+ * region corner tables W[300] = RN(RN(2^nu-1)/t) and R[300] = RN(2^rho-1), and
+ * u = RN(1/t).  Any output pointer may be NULL.  Errors: DMS_EINVAL (t = 0),
+ * DMS_ESPEC.
+ */
+dms_status dms_t_of_k(int32_t k, uint32_t* t);
+dms_status dms_spec_constants(uint64_t seed, uint32_t t, uint64_t keys[6], uint64_t pois[20],
+                              double* W, double* R, double* u);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMS_H */

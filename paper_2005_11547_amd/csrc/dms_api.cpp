@@ -1,0 +1,347 @@
+// C ABI of the DartMinHash library: argument checking, per-t device tables,
+// engine dispatch.  Kernels live in the .hip files.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+
+#include "../../include/dms.h"
+#include "dms_internal.h"
+
+namespace dms {
+hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                               double* out_rank, double phi0, double phi_max, hipStream_t st);
+hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                            int8_t* out_status, double phi0, double phi_max, hipStream_t st);
+hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                              const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                              uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                              double* out_rank, double phi0, double phi_max,
+                              unsigned long long* counter, int blocks, hipStream_t st);
+int fast_waves_per_block(int k);
+__global__ void sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
+                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
+                                   const double* __restrict__ wts, int k, uint32_t* out_u32,
+                                   uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                                   double* out_rank, double phi0, double phi_max,
+                                   unsigned long long* next_set);
+size_t fast_lds_bytes(int k, int waves);
+hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks,
+                     hipStream_t st);
+hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
+                          double* out, hipStream_t st);
+}  // namespace dms
+
+struct dms_ctx_s {
+    int device = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    int engine = DMS_ENGINE_FAST;
+    int n_cu = 0;
+    unsigned long long* counter = nullptr;  // work-stealing cursor of the fast engine
+    double phi0 = 1.0;
+    double lsh_phi0 = 2.0;
+    double phi_max = 1048576.0;
+    std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
+    std::string err;
+};
+
+namespace {
+
+dms_status fail(dms_ctx c, dms_status code, const char* fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+
+dms_status fail(dms_ctx c, dms_status code, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+dms_status hip_fail(dms_ctx c, hipError_t e, const char* what)
+{
+    return fail(c, DMS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device copy of the specification tables for t, created on first use.
+dms_status spec_for(dms_ctx c, uint32_t t, const dms::SpecTables** out)
+{
+    auto it = c->spec.find(t);
+    if (it != c->spec.end()) {
+        *out = it->second;
+        return DMS_OK;
+    }
+    dms::SpecTables host;
+    if (!dms::make_spec(c->seed, t, &host))
+        return fail(c, DMS_ESPEC, "Poisson thresholds could not be derived exactly");
+    dms::SpecTables* dev = nullptr;
+    hipError_t e = hipMalloc((void**)&dev, sizeof host);
+    if (e != hipSuccess) return fail(c, DMS_ENOMEM, "hipMalloc(spec tables): %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(dev, &host, sizeof host, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(c, e, "copy of spec tables");
+    }
+    c->spec[t] = dev;
+    *out = dev;
+    return DMS_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+dms_status dms_create(dms_ctx* out, int device, uint64_t seed)
+{
+    if (!out) return DMS_EINVAL;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return DMS_EHIP;
+    if (device < 0 || device >= n) return DMS_EINVAL;
+    dms_ctx c = new dms_ctx_s;
+    c->device = device;
+    c->seed = seed;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
+        hipMalloc((void**)&c->counter, 64) != hipSuccess) {
+        delete c;
+        return DMS_EHIP;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return DMS_OK;
+}
+
+dms_status dms_destroy(dms_ctx c)
+{
+    if (!c) return DMS_EINVAL;
+    DeviceGuard g(c->device);
+    for (auto& kv : c->spec) (void)hipFree(kv.second);
+    if (c->counter) (void)hipFree(c->counter);
+    delete c;
+    return DMS_OK;
+}
+
+dms_status dms_set_stream(dms_ctx c, void* s)
+{
+    if (!c) return DMS_EINVAL;
+    c->stream = (hipStream_t)s;
+    return DMS_OK;
+}
+
+dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
+{
+    if (!c) return DMS_EINVAL;
+    switch (opt) {
+    case DMS_OPT_ENGINE:
+        if (v != DMS_ENGINE_FAST && v != DMS_ENGINE_PLAIN)
+            return fail(c, DMS_EINVAL, "unknown engine %g", v);
+        c->engine = (int)v;
+        return DMS_OK;
+    case DMS_OPT_PHI0:
+    case DMS_OPT_LSH_PHI0:
+    case DMS_OPT_PHI_MAX:
+        if (!(v > 0.0) || std::isinf(v)) return fail(c, DMS_EINVAL, "phi must be positive and finite");
+        if (opt == DMS_OPT_PHI0) c->phi0 = v;
+        else if (opt == DMS_OPT_LSH_PHI0) c->lsh_phi0 = v;
+        else c->phi_max = v;
+        return DMS_OK;
+    default:
+        return fail(c, DMS_EINVAL, "unknown option %d", opt);
+    }
+}
+
+dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
+{
+    if (!c || !v) return DMS_EINVAL;
+    switch (opt) {
+    case DMS_OPT_ENGINE: *v = c->engine; return DMS_OK;
+    case DMS_OPT_PHI0: *v = c->phi0; return DMS_OK;
+    case DMS_OPT_LSH_PHI0: *v = c->lsh_phi0; return DMS_OK;
+    case DMS_OPT_PHI_MAX: *v = c->phi_max; return DMS_OK;
+    default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
+    }
+}
+
+dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                          const double* w, int32_t k, uint32_t* out_u32, uint64_t* out_bits,
+                          int8_t* out_status, uint64_t* out_s, double* out_rank)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 0) return fail(c, DMS_EINVAL, "n_sets < 0");
+    if (k < 1 || k > 4096) return fail(c, DMS_EINVAL, "k = %d outside 1..4096", k);
+    if (n_sets == 0) return DMS_OK;
+    if (!row_ptr || !idx || !w) return fail(c, DMS_EINVAL, "NULL input pointer");
+    DeviceGuard g(c->device);
+    const dms::SpecTables* sp = nullptr;
+    dms_status st = spec_for(c, dms::t_of_k(k), &sp);
+    if (st != DMS_OK) return st;
+    hipError_t e;
+    // the flattened engine keeps its queues and k buckets in one block's LDS;
+    // beyond 64 KiB the plain engine serves the call
+    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds_bytes(k, 1) > 65536) {
+        e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
+                                     out_status, out_s, out_rank, c->phi0, c->phi_max, c->stream);
+    } else {
+        const int waves = dms::fast_waves_per_block(k);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&dms::sketch_fast_kernel), 64 * waves,
+                dms::fast_lds_bytes(k, waves)) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        e = dms::launch_sketch_fast(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits, out_status,
+                                    out_s, out_rank, c->phi0, c->phi_max, c->counter,
+                                    per_cu * c->n_cu, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
+    return DMS_OK;
+}
+
+dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                        const double* w, int32_t L, int32_t K, uint64_t* out_keys,
+                        int8_t* out_status)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 0) return fail(c, DMS_EINVAL, "n_sets < 0");
+    if (L < 1 || L > 1024 || K < 1 || K > 64 || (int64_t)L * K > 65536)
+        return fail(c, DMS_EINVAL, "L = %d, K = %d out of range", L, K);
+    if (n_sets == 0) return DMS_OK;
+    if (!row_ptr || !idx || !w || !out_keys) return fail(c, DMS_EINVAL, "NULL pointer");
+    if ((size_t)L * K * 16 + (size_t)L * 8 > 65536)
+        return fail(c, DMS_EINVAL, "L*K too large for one wave's tables");
+    DeviceGuard g(c->device);
+    const dms::SpecTables* sp = nullptr;
+    dms_status st = spec_for(c, (uint32_t)(L * K), &sp);
+    if (st != DMS_OK) return st;
+    hipError_t e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
+                                         c->lsh_phi0, c->phi_max, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lsh launch");
+    return DMS_OK;
+}
+
+dms_status dms_jaccard_est(dms_ctx c, int64_t n_pairs, const void* a, const void* b, int32_t k,
+                           int32_t format, double* out)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_pairs < 0 || k < 1 || k > (1 << 20)) return fail(c, DMS_EINVAL, "bad n_pairs or k");
+    if (format != DMS_FMT_U32 && format != DMS_FMT_1BIT) return fail(c, DMS_EINVAL, "bad format");
+    if (n_pairs == 0) return DMS_OK;
+    if (!a || !b || !out) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipError_t e = dms::launch_jaccard(n_pairs, a, b, k, format, out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "jaccard launch");
+    return DMS_OK;
+}
+
+dms_status dms_hamming_topk(dms_ctx c, const uint64_t* db, int64_t n_db, int32_t words,
+                            const uint64_t* queries, int64_t n_q, int32_t topk, int64_t* out_ids,
+                            int32_t* out_dist)
+{
+    (void)db; (void)n_db; (void)words; (void)queries; (void)n_q; (void)topk; (void)out_ids; (void)out_dist;
+    return fail(c, DMS_EINVAL, "hamming top-k not available yet");
+}
+
+dms_status dms_calibrate(dms_ctx c, int32_t kind, int32_t iters, int64_t bytes, int32_t blocks,
+                         void* a, void* b, double* out_ms)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (kind < 0 || kind > 2 || iters < 1 || blocks < 1 || !a || !out_ms ||
+        (kind == 2 && (!b || bytes < 16 || bytes % 16)))
+        return fail(c, DMS_EINVAL, "bad calibration arguments");
+    DeviceGuard g(c->device);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(c, DMS_EHIP, "event");
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(c, DMS_EHIP, "event"); }
+    hipError_t e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) e = dms::calib_run(kind, iters, a, b, bytes, blocks, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(c, e, "calibration");
+    *out_ms = ms;
+    return DMS_OK;
+}
+
+dms_status dms_sync(dms_ctx c)
+{
+    if (!c) return DMS_EINVAL;
+    DeviceGuard g(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+    return DMS_OK;
+}
+
+const char* dms_last_error(dms_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+const char* dms_status_str(dms_status s)
+{
+    switch (s) {
+    case DMS_OK: return "DMS_OK";
+    case DMS_EINVAL: return "DMS_EINVAL";
+    case DMS_EHIP: return "DMS_EHIP";
+    case DMS_ENOMEM: return "DMS_ENOMEM";
+    case DMS_ESPEC: return "DMS_ESPEC";
+    default: return "unknown status";
+    }
+}
+
+dms_status dms_t_of_k(int32_t k, uint32_t* t)
+{
+    if (k < 1 || k > (1 << 20) || !t) return DMS_EINVAL;
+    *t = dms::t_of_k(k);
+    return DMS_OK;
+}
+
+dms_status dms_spec_constants(uint64_t seed, uint32_t t, uint64_t keys[6], uint64_t pois[20],
+                              double* W, double* R, double* u)
+{
+    if (t == 0) return DMS_EINVAL;
+    dms::SpecTables sp;
+    if (!dms::make_spec(seed, t, &sp)) return DMS_ESPEC;
+    if (keys) {
+        keys[0] = sp.key_r; keys[1] = sp.key_a; keys[2] = sp.key_u;
+        keys[3] = sp.key_v; keys[4] = sp.key_s; keys[5] = sp.key_l;
+    }
+    if (pois) std::memcpy(pois, sp.pois, sizeof sp.pois);
+    if (W) std::memcpy(W, sp.W, sizeof sp.W);
+    if (R) std::memcpy(R, sp.R, sizeof sp.R);
+    if (u) *u = sp.u;
+    return DMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device helpers of the DartMinHash kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dms_internal.h"
+
+namespace dms {
+
+constexpr int kWave = 64;
+constexpr uint64_t kRankEmpty = 0x7FF0000000000000ull;  // bit pattern of +inf
+
+// SplitMix64 output function: the specification's 64-bit mixer.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// The 53 high bits of a hash as a uniform double in [0, 1) (exact conversion).
+__device__ __forceinline__ double unit53(uint64_t h)
+{
+    return (double)(h >> 11) * 0x1.0p-53;
+}
+
+// Darts in an area: number of Poisson thresholds at or below the area hash.
+__device__ __forceinline__ uint32_t poisson_count(const uint64_t* __restrict__ pois, uint64_t a)
+{
+    uint32_t x = 0;
+    while (x < (uint32_t)kNumPoisson && a >= pois[x]) ++x;
+    return x;
+}
+
+// bucket = (hi32(s) * n) >> 32
+__device__ __forceinline__ uint32_t bucket_of(uint64_t s, uint32_t n)
+{
+    return (uint32_t)(((s >> 32) * (uint64_t)n) >> 32);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Orders this wave's LDS accesses before and after the call, so that values
+// written by other lanes of the wave are seen by later reads (no hardware
+// barrier: the lanes of a wave execute in lockstep).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+__device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
+
+// Lexicographic (rank, s) minimum of one bucket, shared by the lanes of one
+// wave.  rank is non-negative, so its bit pattern orders like the value.
+// Lanes of the same wave that hit the same bucket in the same instruction are
+// resolved by the three steps; lanes of other waves must not touch the bucket.
+__device__ __forceinline__ void bucket_min(uint64_t* rank_bits, uint64_t* sval, uint32_t b,
+                                           uint64_t rb, uint64_t s)
+{
+    uint64_t old = __hip_atomic_fetch_min(&rank_bits[b], rb, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (rb < old)  // the bucket's rank went down: forget the old id
+        __hip_atomic_store(&sval[b], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint64_t cur = __hip_atomic_load(&rank_bits[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == rb)
+        __hip_atomic_fetch_min(&sval[b], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Validity, positive sum and maximum of one CSR row (lanes over nonzeros).
+struct RowInfo {
+    double sum;
+    int8_t status;
+};
+
+__device__ __forceinline__ RowInfo scan_row(const double* __restrict__ w, int64_t b0, int64_t b1,
+                                            int lane)
+{
+    double sum = 0.0, mx = 0.0;
+    bool bad = false;
+    for (int64_t e = b0 + lane; e < b1; e += kWave) {
+        double v = w[e];
+        if (__builtin_isnan(v) || v < 0.0 || __builtin_isinf(v)) bad = true;
+        if (v > 0.0) {
+            sum += v;
+            mx = fmax(mx, v);
+        }
+    }
+    RowInfo ri;
+    ri.sum = wave_sum(sum);
+    mx = wave_max(mx);
+    if (wave_any(bad)) ri.status = kSetInvalid;
+    else if (!(mx > 0.0)) ri.status = kSetEmpty;
+    else if (mx > 0x1.0p256 || mx < 0x1.0p-256) ri.status = kSetRange;
+    else ri.status = kSetOk;
+    return ri;
+}
+
+}  // namespace dms

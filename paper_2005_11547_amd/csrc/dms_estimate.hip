@@ -1,0 +1,65 @@
+// Weighted Jaccard estimates from sketches (Section 1.1): the fraction of equal
+// minhashes, and 1 - 2 * (disagreeing bits)/k for 1-bit sketches.  Memory
+// bound: one wavefront per pair, lanes over the sketch words, coalesced loads.
+#include "dms_device.h"
+
+namespace dms {
+
+__global__ void __launch_bounds__(256)
+jaccard_u32_kernel(int64_t n_pairs, const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                   int k, double* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < n_pairs;
+         p += waves) {
+        const uint32_t* pa = a + p * k;
+        const uint32_t* pb = b + p * k;
+        uint32_t m = 0;
+        for (int j = lane; j < k; j += kWave) m += pa[j] == pb[j] ? 1u : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o, kWave);
+        if (lane == 0) out[p] = (double)m / (double)k;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+jaccard_1bit_kernel(int64_t n_pairs, const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                    int k, double* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int words = (k + 63) / 64;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < n_pairs;
+         p += waves) {
+        const uint64_t* pa = a + p * words;
+        const uint64_t* pb = b + p * words;
+        uint32_t d = 0;
+        for (int j = lane; j < words; j += kWave) {
+            uint64_t x = pa[j] ^ pb[j];
+            const int valid = k - j * 64;
+            if (valid < 64) x &= (1ull << valid) - 1ull;
+            d += (uint32_t)__popcll(x);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, kWave);
+        if (lane == 0) out[p] = 1.0 - (2.0 * (double)d) / (double)k;
+    }
+}
+
+hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
+                          double* out, hipStream_t st)
+{
+    if (n_pairs <= 0) return hipSuccess;
+    int64_t blocks = (n_pairs + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    if (format == 0)
+        hipLaunchKernelGGL(jaccard_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_pairs,
+                           (const uint32_t*)a, (const uint32_t*)b, k, out);
+    else
+        hipLaunchKernelGGL(jaccard_1bit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_pairs,
+                           (const uint64_t*)a, (const uint64_t*)b, k, out);
+    return hipGetLastError();
+}
+
+}  // namespace dms

@@ -1,0 +1,32 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// DartMinHash library.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <cstdint>
+
+namespace dms {
+
+constexpr int kTable = 300;     // region corner tables, nu and rho < 300
+constexpr int kNumPoisson = 20; // Poisson(1) thresholds for n = 0..19
+
+// Everything a kernel needs to generate darts for one value of t.  Lives in
+// device memory, one copy per t, owned by the context.
+struct SpecTables {
+    double W[kTable];       // W[nu]  = RN(RN(2^nu - 1) / t)
+    double R[kTable];       // R[rho] = RN(2^rho - 1)
+    uint64_t pois[kNumPoisson];
+    uint64_t key_r, key_a, key_u, key_v, key_s, key_l;
+    double u;               // RN(1/t)
+    uint32_t t;
+    uint32_t pad;
+};
+
+uint32_t t_of_k(int32_t k);
+bool poisson_thresholds(uint64_t out[kNumPoisson]);
+void hash_keys(uint64_t seed, uint64_t keys[6]);
+bool make_spec(uint64_t seed, uint32_t t, SpecTables* sp);
+
+// Per-set status values written to out_status.
+enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3 };
+
+}  // namespace dms

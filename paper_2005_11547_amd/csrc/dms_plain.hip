@@ -1,0 +1,268 @@
+// "Plain" DartMinHash and (L,K) LSH kernels: one wavefront per set, one lane
+// per nonzero, Algorithm 1's loops run inside each lane exactly as written
+// (element, nu, rho, w with its exit, r with its exit, j).  One launch covers
+// the whole batch.  These kernels are the simple comparator for the
+// flattened kernels in dms_sketch.hip and share their dart arithmetic.
+#include "dms_device.h"
+
+namespace dms {
+
+// Walks Algorithm 1 for the elements owned by one lane and hands every accepted
+// dart (rank <= tau, weight <= x_i) to `sink(rank, s)`.  Sets *range when an
+// index leaves the supported domain.
+template <class Sink>
+__device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
+                                              const int32_t* __restrict__ idx,
+                                              const double* __restrict__ w, int64_t b0,
+                                              int64_t b1, int lane, double tau, bool* range,
+                                              Sink&& sink)
+{
+    for (int64_t e = b0 + lane; e < b1; e += kWave) {
+        const double xi = w[e];
+        if (!(xi > 0.0)) continue;
+        const uint64_t id = (uint32_t)idx[e];
+        for (int nu = 0; sp->W[nu] <= xi; ++nu) {
+            if (nu + 1 >= kTable) { *range = true; break; }
+            const double Wn = sp->W[nu];
+            for (int rho = 0; sp->R[rho] <= tau; ++rho) {
+                if (rho + 1 >= kTable) { *range = true; break; }
+                const double Rr = sp->R[rho];
+                const double dnu = ldexp(sp->u, nu - rho);
+                const double drho = ldexp(1.0, rho - nu);
+                const uint64_t g =
+                    mix64(sp->key_r ^ ((id << 32) | ((uint64_t)nu << 16) | (uint64_t)rho));
+                for (uint64_t wc = 0;; ++wc) {
+                    if (rho < 63 && wc >= (1ull << rho)) break;
+                    const double wd = (double)wc;
+                    if (xi < Wn + wd * dnu) break;
+                    if (wc >= 0x100000000ull) { *range = true; break; }
+                    for (uint64_t rc = 0;; ++rc) {
+                        if (nu < 63 && rc >= (1ull << nu)) break;
+                        const double rd = (double)rc;
+                        if (tau < Rr + rd * drho) break;
+                        if (rc >= 0x100000000ull) { *range = true; break; }
+                        const uint64_t a = mix64(g ^ sp->key_a ^ ((wc << 32) | rc));
+                        const uint32_t X = poisson_count(sp->pois, a);
+                        for (uint32_t j = 0; j < X; ++j) {
+                            const double U = unit53(mix64(a ^ sp->key_u ^ (uint64_t)j));
+                            const double rank = Rr + (rd + U) * drho;
+                            if (!(rank <= tau)) continue;
+                            const double V = unit53(mix64(a ^ sp->key_v ^ (uint64_t)j));
+                            const double weight = Wn + (wd + V) * dnu;
+                            if (!(weight <= xi)) continue;
+                            sink(rank, mix64(a ^ sp->key_s ^ (uint64_t)j));
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void write_minhash(int64_t set, int k, int lane, int8_t status,
+                                              const uint64_t* rank_bits, const uint64_t* sval,
+                                              uint32_t* out_u32, uint64_t* out_bits,
+                                              int8_t* out_status, uint64_t* out_s,
+                                              double* out_rank)
+{
+    const bool ok = status == kSetOk;
+    for (int j = lane; j < k; j += kWave) {
+        const uint64_t s = ok ? sval[j] : ~0ull;
+        const uint64_t rb = ok ? rank_bits[j] : kRankEmpty;
+        if (out_u32) out_u32[set * k + j] = ok ? (uint32_t)s : 0xFFFFFFFFu;
+        if (out_s) out_s[set * k + j] = s;
+        if (out_rank) out_rank[set * k + j] = __longlong_as_double((long long)rb);
+    }
+    if (out_bits) {
+        const int words = (k + 63) / 64;
+        for (int wd = 0; wd < words; ++wd) {
+            const int j = wd * 64 + lane;
+            const bool bit = ok && j < k && (sval[j] & 1ull);
+            const uint64_t word = __ballot(bit);
+            if (lane == 0) out_bits[(int64_t)set * words + wd] = word;
+        }
+    }
+    if (out_status && lane == 0) out_status[set] = status;
+}
+
+// grid: ceil(n_sets / waves) blocks of 64*waves threads; LDS: waves * 16 k bytes.
+__global__ void __launch_bounds__(256)
+sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
+                    const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
+                    const double* __restrict__ w, int k, uint32_t* out_u32, uint64_t* out_bits,
+                    int8_t* out_status, uint64_t* out_s, double* out_rank, double phi0,
+                    double phi_max)
+{
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t set = (int64_t)blockIdx.x * waves + wave;
+    if (set >= n_sets) return;  // whole wave leaves; no block barrier follows
+    uint64_t* rank_bits = lds + (size_t)wave * 2 * k;
+    uint64_t* sval = rank_bits + k;
+
+    const int64_t b0 = rp[set], b1 = rp[set + 1];
+    const RowInfo ri = scan_row(w, b0, b1, lane);
+    int8_t status = ri.status;
+    if (status == kSetOk) {
+        for (int j = lane; j < k; j += kWave) {
+            rank_bits[j] = kRankEmpty;
+            sval[j] = ~0ull;
+        }
+        double phi = phi0;
+        for (;;) {
+            if (phi > phi_max) { status = kSetRange; break; }
+            const double tau = phi / ri.sum;
+            bool range = false;
+            lane_darthash(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
+                bucket_min(rank_bits, sval, bucket_of(s, (uint32_t)k),
+                           (uint64_t)__double_as_longlong(rank), s);
+            });
+            if (wave_any(range)) { status = kSetRange; break; }
+            wave_sync();
+            bool filled = true;
+            for (int j = lane; j < k; j += kWave) filled &= rank_bits[j] != kRankEmpty;
+            if (wave_all(filled)) break;
+            phi *= 2.0;
+        }
+    }
+    wave_sync();
+    write_minhash(set, k, lane, status, rank_bits, sval, out_u32, out_bits, out_status, out_s,
+                  out_rank);
+}
+
+// ---------------------------------------------------------------------------
+// (L,K) LSH.  Each table keeps its K smallest (rank, s) in ascending order in
+// LDS; lanes holding a dart at the same time insert one after another.
+struct LshLds {
+    uint64_t* rank;   // [L*K]
+    uint64_t* sval;   // [L*K]
+    int32_t* cnt;     // [L]
+};
+
+__device__ __forceinline__ void lsh_insert(const LshLds& T, int K, uint32_t l, uint64_t rb,
+                                           uint64_t s)
+{
+    uint64_t* r = T.rank + (size_t)l * K;
+    uint64_t* v = T.sval + (size_t)l * K;
+    const int c = T.cnt[l];
+    int pos = 0;
+    for (int m = 0; m < c; ++m) {
+        if (r[m] == rb && v[m] == s) return;  // already held (repeated element id)
+        pos += (r[m] < rb || (r[m] == rb && v[m] < s)) ? 1 : 0;
+    }
+    if (pos >= K) return;
+    const int last = c < K ? c : K - 1;
+    for (int m = last; m > pos; --m) {
+        r[m] = r[m - 1];
+        v[m] = v[m - 1];
+    }
+    r[pos] = rb;
+    v[pos] = s;
+    if (c < K) T.cnt[l] = c + 1;
+}
+
+// LDS per wave: L*K*16 + L*8 bytes.
+__global__ void __launch_bounds__(256)
+lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
+                 const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
+                 const double* __restrict__ w, int L, int K, uint64_t* out_keys,
+                 int8_t* out_status, double phi0, double phi_max)
+{
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t set = (int64_t)blockIdx.x * waves + wave;
+    if (set >= n_sets) return;
+    const size_t per_wave = (size_t)2 * L * K + L;  // in 8-byte words
+    uint64_t* base = lds + (size_t)wave * per_wave;
+    LshLds T;
+    T.rank = base;
+    T.sval = base + (size_t)L * K;
+    T.cnt = (int32_t*)(base + (size_t)2 * L * K);
+
+    const int64_t b0 = rp[set], b1 = rp[set + 1];
+    const RowInfo ri = scan_row(w, b0, b1, lane);
+    int8_t status = ri.status;
+    if (status == kSetOk) {
+        for (int l = lane; l < L; l += kWave) T.cnt[l] = 0;
+        double phi = phi0;
+        for (;;) {
+            if (phi > phi_max) { status = kSetRange; break; }
+            const double tau = phi / ri.sum;
+            bool range = false;
+            lane_darthash(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
+                const uint32_t l = bucket_of(s, (uint32_t)L);
+                const uint64_t rb = (uint64_t)__double_as_longlong(rank);
+                // lanes reaching this point together may target the same table:
+                // they insert one after another, lowest lane first
+                uint64_t active = __ballot(true);
+                while (active) {
+                    const int ln = __ffsll((unsigned long long)active) - 1;
+                    if (lane == ln) lsh_insert(T, K, l, rb, s);
+                    active &= active - 1;
+                }
+            });
+            if (wave_any(range)) { status = kSetRange; break; }
+            wave_sync();
+            bool full = true;
+            for (int l = lane; l < L; l += kWave) full &= T.cnt[l] >= K;
+            if (wave_all(full)) break;
+            phi *= 2.0;
+        }
+    }
+    wave_sync();
+    for (int l = lane; l < L; l += kWave) {
+        uint64_t h = 0;
+        if (status == kSetOk) {
+            h = mix64(sp->key_l ^ (uint64_t)l);
+            for (int m = 0; m < K; ++m) h = mix64(h ^ T.sval[(size_t)l * K + m]);
+        }
+        out_keys[set * L + l] = h;
+    }
+    if (out_status && lane == 0) out_status[set] = status;
+}
+
+}  // namespace dms
+
+namespace dms {
+
+int plain_waves_per_block(int k)
+{
+    int w = 65536 / (16 * k);
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                               double* out_rank, double phi0, double phi_max, hipStream_t st)
+{
+    if (n_sets <= 0) return hipSuccess;
+    const int waves = plain_waves_per_block(k);
+    const int64_t blocks = (n_sets + waves - 1) / waves;
+    const size_t lds = (size_t)waves * 16 * k;
+    hipLaunchKernelGGL(sketch_plain_kernel, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+                       n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s, out_rank,
+                       phi0, phi_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                            int8_t* out_status, double phi0, double phi_max, hipStream_t st)
+{
+    if (n_sets <= 0) return hipSuccess;
+    const size_t per_wave = ((size_t)2 * L * K + L) * 8;
+    int waves = (int)(65536 / per_wave);
+    waves = waves < 1 ? 1 : (waves > 4 ? 4 : waves);
+    const int64_t blocks = (n_sets + waves - 1) / waves;
+    hipLaunchKernelGGL(lsh_plain_kernel, dim3((unsigned)blocks), dim3(64 * waves),
+                       per_wave * waves, st, sp, n_sets, rp, idx, w, L, K, out_keys, out_status,
+                       phi0, phi_max);
+    return hipGetLastError();
+}
+
+}  // namespace dms

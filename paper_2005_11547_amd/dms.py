@@ -1,0 +1,219 @@
+"""Python binding of the DartMinHash C ABI (include/dms.h).
+
+Argument marshalling only: every step of the sketching path runs in the HIP
+kernels of ``libdms.so``.  PyTorch provides device memory and the stream.
+The binding raises if the library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdms.so")
+
+DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
+SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
+ENGINE_FAST, ENGINE_PLAIN = 0, 1
+OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX = 0, 1, 2, 3
+FMT_U32, FMT_1BIT = 0, 1
+
+EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
+           "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
+           "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate"]
+
+_lib = None
+
+
+class DMSError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libdms.so (built by paper_2005_11547_amd/build_lib.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise DMSError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "dms_create": ([P(vp), ctypes.c_int, u64], i32),
+        "dms_destroy": ([vp], i32),
+        "dms_set_stream": ([vp, vp], i32),
+        "dms_set_option": ([vp, i32, f64], i32),
+        "dms_get_option": ([vp, i32, P(f64)], i32),
+        "dms_sketch_csr": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
+        "dms_lsh_keys": ([vp, i64, vp, vp, vp, i32, i32, vp, vp], i32),
+        "dms_jaccard_est": ([vp, i64, vp, vp, i32, i32, vp], i32),
+        "dms_hamming_topk": ([vp, vp, i64, i32, vp, i64, i32, vp, vp], i32),
+        "dms_sync": ([vp], i32),
+        "dms_last_error": ([vp], ctypes.c_char_p),
+        "dms_status_str": ([i32], ctypes.c_char_p),
+        "dms_t_of_k": ([i32, P(u32)], i32),
+        "dms_spec_constants": ([u64, u32, vp, vp, vp, vp, vp], i32),
+        "dms_calibrate": ([vp, i32, i32, i64, i32, vp, vp, P(f64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / numpy array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(ctypes.c_void_p)
+
+
+def t_of_k(k: int) -> int:
+    t = ctypes.c_uint32(0)
+    st = lib().dms_t_of_k(k, ctypes.byref(t))
+    if st != DMS_OK:
+        raise DMSError(f"dms_t_of_k({k}) -> {st}")
+    return t.value
+
+
+def spec_constants(seed: int, t: int) -> dict:
+    """The library's own derivation of the specification constants (host only)."""
+    import numpy as np
+    keys = np.zeros(6, np.uint64)
+    pois = np.zeros(20, np.uint64)
+    W = np.zeros(300, np.float64)
+    R = np.zeros(300, np.float64)
+    u = ctypes.c_double(0.0)
+    st = lib().dms_spec_constants(seed, t, _ptr(keys), _ptr(pois), _ptr(W), _ptr(R), ctypes.byref(u))
+    if st != DMS_OK:
+        raise DMSError(f"dms_spec_constants -> {st}")
+    return dict(keys=keys, pois=pois, W=W, R=R, u=u.value)
+
+
+class Context:
+    """One dms_ctx on a GPU; calls run on torch's current stream of that device."""
+
+    def __init__(self, seed: int, device: int = 0, engine: int | None = None):
+        import torch
+        self.device = device
+        self._h = ctypes.c_void_p()
+        self._check(lib().dms_create(ctypes.byref(self._h), device, seed), "dms_create")
+        self.seed = seed
+        if engine is not None:
+            self.set_option(OPT_ENGINE, engine)
+        self._torch = torch
+
+    def _check(self, st, what):
+        if st != DMS_OK:
+            msg = lib().dms_last_error(self._h).decode() if getattr(self, "_h", None) else ""
+            raise DMSError(f"{what}: {lib().dms_status_str(st).decode()} {msg}")
+
+    def close(self):
+        if self._h:
+            lib().dms_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = self._torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib().dms_set_stream(self._h, ctypes.c_void_p(s)), "dms_set_stream")
+
+    def set_option(self, opt: int, value: float):
+        self._check(lib().dms_set_option(self._h, opt, float(value)), "dms_set_option")
+
+    def get_option(self, opt: int) -> float:
+        v = ctypes.c_double(0.0)
+        self._check(lib().dms_get_option(self._h, opt, ctypes.byref(v)), "dms_get_option")
+        return v.value
+
+    # -- raw C-ABI calls on device tensors -----------------------------------
+    def dms_sketch_csr(self, n_sets, row_ptr, idx, w, k, out_u32=None, out_bits=None,
+                       out_status=None, out_s=None, out_rank=None):
+        self._stream()
+        self._check(lib().dms_sketch_csr(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
+                                         _ptr(out_u32), _ptr(out_bits), _ptr(out_status),
+                                         _ptr(out_s), _ptr(out_rank)), "dms_sketch_csr")
+
+    def dms_lsh_keys(self, n_sets, row_ptr, idx, w, L, K, out_keys, out_status=None):
+        self._stream()
+        self._check(lib().dms_lsh_keys(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
+                                       _ptr(out_keys), _ptr(out_status)), "dms_lsh_keys")
+
+    def dms_jaccard_est(self, n_pairs, a, b, k, fmt, out):
+        self._stream()
+        self._check(lib().dms_jaccard_est(self._h, n_pairs, _ptr(a), _ptr(b), k, fmt, _ptr(out)),
+                    "dms_jaccard_est")
+
+    def dms_hamming_topk(self, db, n_db, words, queries, n_q, topk, out_ids, out_dist):
+        self._stream()
+        self._check(lib().dms_hamming_topk(self._h, _ptr(db), n_db, words, _ptr(queries), n_q, topk,
+                                           _ptr(out_ids), _ptr(out_dist)), "dms_hamming_topk")
+
+    def calibrate(self, kind, iters, blocks, a, b=None, nbytes=0):
+        """Run one calibration kernel (see dms_calibrate); returns its duration in ms."""
+        self._stream()
+        ms = ctypes.c_double(0.0)
+        self._check(lib().dms_calibrate(self._h, kind, iters, nbytes, blocks, _ptr(a), _ptr(b),
+                                        ctypes.byref(ms)), "dms_calibrate")
+        return ms.value
+
+    def sync(self):
+        self._check(lib().dms_sync(self._h), "dms_sync")
+
+    # -- conveniences that allocate outputs ----------------------------------
+    def sketch(self, row_ptr, idx, w, k, bits=True, full=False):
+        """Sketch a CSR batch already on the GPU; returns a dict of device tensors."""
+        torch = self._torch
+        n = row_ptr.numel() - 1
+        dev = row_ptr.device
+        out = dict(u32=torch.empty((n, k), dtype=torch.int32, device=dev),
+                   status=torch.empty(n, dtype=torch.int8, device=dev))
+        if bits:
+            out["bits"] = torch.empty((n, (k + 63) // 64), dtype=torch.int64, device=dev)
+        if full:
+            out["s"] = torch.empty((n, k), dtype=torch.int64, device=dev)
+            out["rank"] = torch.empty((n, k), dtype=torch.float64, device=dev)
+        self.dms_sketch_csr(n, row_ptr, idx, w, k, out["u32"], out.get("bits"), out["status"],
+                            out.get("s"), out.get("rank"))
+        return out
+
+    def lsh(self, row_ptr, idx, w, L, K):
+        torch = self._torch
+        n = row_ptr.numel() - 1
+        dev = row_ptr.device
+        out = dict(keys=torch.empty((n, L), dtype=torch.int64, device=dev),
+                   status=torch.empty(n, dtype=torch.int8, device=dev))
+        self.dms_lsh_keys(n, row_ptr, idx, w, L, K, out["keys"], out["status"])
+        return out
+
+    def jaccard(self, a, b, k, fmt):
+        torch = self._torch
+        out = torch.empty(a.shape[0], dtype=torch.float64, device=a.device)
+        self.dms_jaccard_est(a.shape[0], a, b, k, fmt, out)
+        return out
+
+    def hamming_topk(self, db, queries, topk):
+        torch = self._torch
+        nq, words = queries.shape
+        ids = torch.empty((nq, topk), dtype=torch.int64, device=db.device)
+        dist = torch.empty((nq, topk), dtype=torch.int32, device=db.device)
+        self.dms_hamming_topk(db, db.shape[0], words, queries, nq, topk, ids, dist)
+        return ids, dist
+
+
+def to_device(row_ptr, idx, w, device="cuda"):
+    """Copy a host CSR batch (numpy) to device tensors."""
+    import torch
+    return (torch.from_numpy(row_ptr).to(device), torch.from_numpy(idx).to(device),
+            torch.from_numpy(w).to(device))
