@@ -70,67 +70,49 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint32_t poisson_fast(const uint64_t* __restrict__ pois, uint64_t a)
+// Poisson(1) dart count of an area hash.  C holds the first eight thresholds
+// in registers; `pois` (LDS) the full table for the rare tail.
+__device__ __forceinline__ uint32_t poisson_fast(const uint64_t (&C)[8], const uint64_t* pois,
+                                                 uint64_t a)
 {
-    uint32_t x = (a >= pois[0]) + (a >= pois[1]) + (a >= pois[2]) + (a >= pois[3]) +
-                 (a >= pois[4]) + (a >= pois[5]) + (a >= pois[6]) + (a >= pois[7]);
+    uint32_t x = (a >= C[0]) + (a >= C[1]) + (a >= C[2]) + (a >= C[3]) + (a >= C[4]) +
+                 (a >= C[5]) + (a >= C[6]) + (a >= C[7]);
     if (x == 8) {
         while (x < (uint32_t)kNumPoisson && a >= pois[x]) ++x;
     }
     return x;
 }
 
-// LDS of one wave.
-struct Queues {
-    uint64_t* rank_bits;  // [k] bucket minima
-    uint64_t* sval;       // [k]
-    uint64_t* rq_g;       // region queue
-    double* rq_x;
-    uint32_t* rq_rc;      // rows of the region
-    uint32_t* rq_na;      // areas of the region
-    uint32_t* rq_first;   // areas already taken
-    uint32_t* rq_m;       // nu | rho << 9
-    uint64_t* dq_a;       // dart queue: area hash
-    double* dq_x;
-    uint32_t* dq_r;
-    uint32_t* dq_w;
-    uint32_t* dq_m;       // nu | rho << 9 | j << 18 | X << 23
-    uint64_t* pq_a;       // pass queue
-    double* pq_x;
-    uint64_t* pq_rank;
-    uint32_t* pq_w;
-    uint32_t* pq_m;       // nu | rho << 9 | j << 18
-    int32_t* mark;        // [64]
-};
+// LDS of one wave: queues at fixed offsets from the wave's base, then the k
+// bucket minima.  Offsets are compile-time constants so that every access is
+// one base register plus an immediate.
+constexpr uint32_t kOffRqG = 0;                              // u64[kCapR] region hash
+constexpr uint32_t kOffRqX = kOffRqG + 8 * kCapR;            // f64[kCapR] element weight
+constexpr uint32_t kOffDqA = kOffRqX + 8 * kCapR;            // u64[kCapD] area hash
+constexpr uint32_t kOffDqX = kOffDqA + 8 * kCapD;            // f64[kCapD]
+constexpr uint32_t kOffPqA = kOffDqX + 8 * kCapD;            // u64[kCapP]
+constexpr uint32_t kOffPqX = kOffPqA + 8 * kCapP;            // f64[kCapP]
+constexpr uint32_t kOffPqRank = kOffPqX + 8 * kCapP;         // u64[kCapP] rank bits
+constexpr uint32_t kOffRqRc = kOffPqRank + 8 * kCapP;        // u32[kCapR] rows
+constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCapR;          // u32[kCapR] areas
+constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCapR;       // u32[kCapR] areas taken
+constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | rho << 9
+constexpr uint32_t kOffDqR = kOffRqM + 4 * kCapR;            // u32[kCapD]
+constexpr uint32_t kOffDqW = kOffDqR + 4 * kCapD;            // u32[kCapD]
+constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<9|j<<18|X<<23
+constexpr uint32_t kOffPqW = kOffDqM + 4 * kCapD;            // u32[kCapP]
+constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<9|j<<18
+constexpr uint32_t kOffMark = kOffPqM + 4 * kCapP;           // i32[64]
+constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits, u64[k] ids
+constexpr uint32_t kQueueBytes = kOffBins;
+constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
 
-__host__ __device__ constexpr size_t wave_lds_bytes(int k)
-{
-    return (size_t)16 * k + (size_t)kCapR * 32 + (size_t)kCapD * 28 + (size_t)kCapP * 32 + 64 * 4;
-}
+__host__ __device__ constexpr size_t wave_lds_bytes(int k) { return kQueueBytes + (size_t)16 * k; }
 
-__device__ __forceinline__ Queues carve(unsigned char* p, int k)
+template <class T>
+__device__ __forceinline__ T& at(unsigned char* base, uint32_t off, uint32_t i)
 {
-    Queues q;
-    q.rank_bits = (uint64_t*)p; p += 8 * (size_t)k;
-    q.sval = (uint64_t*)p; p += 8 * (size_t)k;
-    q.rq_g = (uint64_t*)p; p += 8 * kCapR;
-    q.rq_x = (double*)p; p += 8 * kCapR;
-    q.dq_a = (uint64_t*)p; p += 8 * kCapD;
-    q.dq_x = (double*)p; p += 8 * kCapD;
-    q.pq_a = (uint64_t*)p; p += 8 * kCapP;
-    q.pq_x = (double*)p; p += 8 * kCapP;
-    q.pq_rank = (uint64_t*)p; p += 8 * kCapP;
-    q.rq_rc = (uint32_t*)p; p += 4 * kCapR;
-    q.rq_na = (uint32_t*)p; p += 4 * kCapR;
-    q.rq_first = (uint32_t*)p; p += 4 * kCapR;
-    q.rq_m = (uint32_t*)p; p += 4 * kCapR;
-    q.dq_r = (uint32_t*)p; p += 4 * kCapD;
-    q.dq_w = (uint32_t*)p; p += 4 * kCapD;
-    q.dq_m = (uint32_t*)p; p += 4 * kCapD;
-    q.pq_w = (uint32_t*)p; p += 4 * kCapP;
-    q.pq_m = (uint32_t*)p; p += 4 * kCapP;
-    q.mark = (int32_t*)p;
-    return q;
+    return reinterpret_cast<T*>(base + off)[i];
 }
 
 // Number of c in [0, cap) with base + c * step <= bound (an exit predicate
@@ -160,20 +142,26 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
     double* sR = sW + kTable;
+    uint64_t* sPois = (uint64_t*)(sR + kTable);
     for (int i = threadIdx.x; i < kTable; i += blockDim.x) {
         sW[i] = sp->W[i];
         sR[i] = sp->R[i];
     }
+    if (threadIdx.x < kNumPoisson) sPois[threadIdx.x] = sp->pois[threadIdx.x];
     __syncthreads();  // the only block barrier
+    uint64_t C[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) C[i] = sPois[i];  // per-lane copies keep scalar registers free
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    Queues Q = carve(smem + 16 * kTable + (size_t)wave * wave_lds_bytes(k), k);
+    unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(k);
+    uint64_t* const bin_rank = reinterpret_cast<uint64_t*>(wb + kOffBins);
+    uint64_t* const bin_s = bin_rank + k;
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
     const double u = sp->u;
     const double td = (double)sp->t;
-    const uint64_t* pois = sp->pois;
 
     for (;;) {
         unsigned long long got = 0;
@@ -186,8 +174,8 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
         int8_t status = ri.status;
         if (status == kSetOk) {
             for (int j = lane; j < k; j += kWave) {
-                Q.rank_bits[j] = kRankEmpty;
-                Q.sval[j] = ~0ull;
+                bin_rank[j] = kRankEmpty;
+                bin_s[j] = ~0ull;
             }
             double phi = phi0;
             double tau_prev = -1.0;  // darts of rank <= tau_prev are already in the buckets
@@ -209,7 +197,7 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                 bool have_chunk = false;
                 uint32_t rq_head = 0, rq_count = 0, dq_head = 0, dq_count = 0;
                 uint32_t pq_head = 0, pq_count = 0;
-                uint64_t rq_pending = 0;   // areas left in the region queue
+                uint32_t rq_pending = 0;   // lower bound of the areas left in the region queue
 
                 auto load_chunk = [&]() {
                     have_chunk = false;
@@ -246,39 +234,33 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                     if (pq_count >= 64 || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- accept round ----------------
                         const uint32_t m = pq_count < 64 ? pq_count : 64;
-                        if ((uint32_t)lane < m) {
-                            const uint32_t pos = (pq_head + lane) & (kCapP - 1);
-                            const uint64_t a = Q.pq_a[pos];
-                            const double xi = Q.pq_x[pos];
-                            const uint32_t wv = Q.pq_w[pos];
-                            const uint32_t meta = Q.pq_m[pos];
-                            const uint64_t rb = Q.pq_rank[pos];
-                            const int nu = meta & 511, rho = (meta >> 9) & 511;
-                            const uint64_t j = (meta >> 18) & 31;
-                            const double V = unit53(mix64(a ^ KV ^ j));
-                            const double weight = sW[nu] + ((double)wv + V) * ldexp(u, nu - rho);
-                            if (weight <= xi) {
-                                const uint64_t s = mix64(a ^ KS ^ j);
-                                bucket_min(Q.rank_bits, Q.sval, bucket_of(s, (uint32_t)k), rb, s);
-                            }
+                        // lanes past m reread the last entry and stay inactive
+                        const uint32_t pos = (pq_head + ((uint32_t)lane < m ? (uint32_t)lane : m - 1)) & (kCapP - 1);
+                        const uint64_t a = at<uint64_t>(wb, kOffPqA, pos);
+                        const double xi = at<double>(wb, kOffPqX, pos);
+                        const uint32_t wv = at<uint32_t>(wb, kOffPqW, pos);
+                        const uint32_t meta = at<uint32_t>(wb, kOffPqM, pos);
+                        const uint64_t rb = at<uint64_t>(wb, kOffPqRank, pos);
+                        const int nu = meta & 511, rho = (meta >> 9) & 511;
+                        const uint64_t j = (meta >> 18) & 31;
+                        const double V = unit53(mix64(a ^ KV ^ j));
+                        const double weight = sW[nu] + ((double)wv + V) * ldexp(u, nu - rho);
+                        if ((uint32_t)lane < m && weight <= xi) {
+                            const uint64_t s = mix64(a ^ KS ^ j);
+                            bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
                         }
-                        pq_head = (pq_head + m) & (kCapP - 1);
-                        pq_count -= m;
+                        pq_head = uni((pq_head + m) & (kCapP - 1));
+                        pq_count = uni(pq_count - m);
                     } else if (dq_count >= 64 || (dq_count > 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- dart round ----------------
                         const uint32_t m = dq_count < 64 ? dq_count : 64;
                         const bool act = (uint32_t)lane < m;
-                        uint64_t a = 0;
-                        double xi = 0.0;
-                        uint32_t rv = 0, wv = 0, meta = 0;
-                        if (act) {
-                            const uint32_t pos = (dq_head + lane) & (kCapD - 1);
-                            a = Q.dq_a[pos];
-                            xi = Q.dq_x[pos];
-                            rv = Q.dq_r[pos];
-                            wv = Q.dq_w[pos];
-                            meta = Q.dq_m[pos];
-                        }
+                        const uint32_t rpos = (dq_head + (act ? (uint32_t)lane : m - 1)) & (kCapD - 1);
+                        const uint64_t a = at<uint64_t>(wb, kOffDqA, rpos);
+                        const double xi = at<double>(wb, kOffDqX, rpos);
+                        const uint32_t rv = at<uint32_t>(wb, kOffDqR, rpos);
+                        const uint32_t wv = at<uint32_t>(wb, kOffDqW, rpos);
+                        const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
                         const int nu = meta & 511, rho = (meta >> 9) & 511;
                         const uint32_t j = (meta >> 18) & 31, X = meta >> 23;
                         const double U = unit53(mix64(a ^ KU ^ (uint64_t)j));
@@ -290,32 +272,32 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                         wave_sync();  // every entry of the round is read before any write
                         if (pass) {
                             const uint32_t pos = (pq_head + pq_count + rank_in(bp)) & (kCapP - 1);
-                            Q.pq_a[pos] = a;
-                            Q.pq_x[pos] = xi;
-                            Q.pq_rank[pos] = (uint64_t)__double_as_longlong(rank);
-                            Q.pq_w[pos] = wv;
-                            Q.pq_m[pos] = meta & ((1u << 23) - 1);
+                            at<uint64_t>(wb, kOffPqA, pos) = a;
+                            at<double>(wb, kOffPqX, pos) = xi;
+                            at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
+                            at<uint32_t>(wb, kOffPqW, pos) = wv;
+                            at<uint32_t>(wb, kOffPqM, pos) = meta & ((1u << 23) - 1);
                         }
                         const uint32_t dq_left = dq_count - m;
                         if (more) {
                             const uint32_t pos = (dq_head + m + dq_left + rank_in(bm)) & (kCapD - 1);
-                            Q.dq_a[pos] = a;
-                            Q.dq_x[pos] = xi;
-                            Q.dq_r[pos] = rv;
-                            Q.dq_w[pos] = wv;
-                            Q.dq_m[pos] = meta + (1u << 18);
+                            at<uint64_t>(wb, kOffDqA, pos) = a;
+                            at<double>(wb, kOffDqX, pos) = xi;
+                            at<uint32_t>(wb, kOffDqR, pos) = rv;
+                            at<uint32_t>(wb, kOffDqW, pos) = wv;
+                            at<uint32_t>(wb, kOffDqM, pos) = meta + (1u << 18);
                         }
-                        pq_count += (uint32_t)__popcll(bp);
-                        dq_head = (dq_head + m) & (kCapD - 1);
-                        dq_count = dq_left + (uint32_t)__popcll(bm);
-                    } else if (rq_pending >= 64 || (rq_count > 0 && !have_chunk)) {
+                        pq_count = uni(pq_count + (uint32_t)__popcll(bp));
+                        dq_head = uni((dq_head + m) & (kCapD - 1));
+                        dq_count = uni(dq_left + (uint32_t)__popcll(bm));
+                    } else if (rq_pending >= 64 || rq_count >= 64 || (rq_count > 0 && !have_chunk)) {
                         // ---------------- area round ----------------
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
                         if ((uint32_t)lane < n_items) {
                             const uint32_t ip = (rq_head + lane) & (kCapR - 1);
-                            na = Q.rq_na[ip];
-                            first = Q.rq_first[ip];
+                            na = at<uint32_t>(wb, kOffRqNa, ip);
+                            first = at<uint32_t>(wb, kOffRqFirst, ip);
                             c = na - first;
                         }
                         const uint32_t cc = c < 64 ? c : 64;
@@ -327,11 +309,11 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                             range = true;
                             break;
                         }
-                        Q.mark[lane] = 0;
+                        at<int32_t>(wb, kOffMark, lane) = 0;
                         wave_sync();
-                        if (cc > 0 && excl < 64) Q.mark[excl] = lane;
+                        if (cc > 0 && excl < 64) at<int32_t>(wb, kOffMark, excl) = lane;
                         wave_sync();
-                        const int32_t src = scan_max(Q.mark[lane]);
+                        const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
                         const uint32_t s_excl = (uint32_t)__shfl(excl, src, kWave);
                         const uint32_t s_first = (uint32_t)__shfl(first, src, kWave);
                         const uint32_t local = s_first + (uint32_t)lane - s_excl;
@@ -341,11 +323,11 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                         double xi = 0.0;
                         if (act) {
                             const uint32_t ip = (rq_head + (uint32_t)src) & (kCapR - 1);
-                            const uint64_t g = Q.rq_g[ip];
-                            xi = Q.rq_x[ip];
-                            const uint32_t rc = Q.rq_rc[ip];
-                            const uint32_t nai = Q.rq_na[ip];
-                            meta = Q.rq_m[ip];
+                            const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
+                            xi = at<double>(wb, kOffRqX, ip);
+                            const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
+                            const uint32_t nai = at<uint32_t>(wb, kOffRqNa, ip);
+                            meta = at<uint32_t>(wb, kOffRqM, ip);
                             if (rc == 1) {
                                 wv = local;
                             } else if (nai == rc) {
@@ -355,42 +337,42 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                                 rv = local - wv * rc;
                             }
                             a = mix64(g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                            X = poisson_fast(pois, a);
+                            X = poisson_fast(C, sPois, a);
                         }
                         const bool push = act && X > 0;
                         const uint64_t bpush = __ballot(push);
                         if (push) {
                             const uint32_t pos = (dq_head + dq_count + rank_in(bpush)) & (kCapD - 1);
-                            Q.dq_a[pos] = a;
-                            Q.dq_x[pos] = xi;
-                            Q.dq_r[pos] = rv;
-                            Q.dq_w[pos] = wv;
-                            Q.dq_m[pos] = meta | (X << 23);
+                            at<uint64_t>(wb, kOffDqA, pos) = a;
+                            at<double>(wb, kOffDqX, pos) = xi;
+                            at<uint32_t>(wb, kOffDqR, pos) = rv;
+                            at<uint32_t>(wb, kOffDqW, pos) = wv;
+                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 23);
                         }
-                        dq_count += (uint32_t)__popcll(bpush);
+                        dq_count = uni(dq_count + (uint32_t)__popcll(bpush));
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
                         const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
                         const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
                         if (last_local + 1 == last_na) {
-                            rq_head = (rq_head + last_src + 1) & (kCapR - 1);
-                            rq_count -= last_src + 1;
+                            rq_head = uni((rq_head + last_src + 1) & (kCapR - 1));
+                            rq_count = uni(rq_count - (last_src + 1));
                         } else {
-                            if (lane == 0) Q.rq_first[(rq_head + last_src) & (kCapR - 1)] = last_local + 1;
-                            rq_head = (rq_head + last_src) & (kCapR - 1);
-                            rq_count -= last_src;
+                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, (rq_head + last_src) & (kCapR - 1)) = last_local + 1;
+                            rq_head = uni((rq_head + last_src) & (kCapR - 1));
+                            rq_count = uni(rq_count - last_src);
                         }
-                        rq_pending -= m;
+                        rq_pending = rq_pending > m ? uni(rq_pending - m) : 0u;
                     } else if (have_chunk) {
                         // ---------------- region round ----------------
                         const uint32_t left = chunk_total - reg_done;
                         const uint32_t m = left < 64 ? left : 64;
-                        Q.mark[lane] = 0;
+                        at<int32_t>(wb, kOffMark, lane) = 0;
                         wave_sync();
                         if (nreg > 0 && nreg_excl + nreg > reg_done && nreg_excl < reg_done + 64)
-                            Q.mark[nreg_excl > reg_done ? nreg_excl - reg_done : 0] = lane;
+                            at<int32_t>(wb, kOffMark, nreg_excl > reg_done ? nreg_excl - reg_done : 0) = lane;
                         wave_sync();
-                        const int32_t src = scan_max(Q.mark[lane]);
+                        const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
                         const double x = __shfl(ex, src, kWave);
                         const uint32_t id = (uint32_t)__shfl(eid, src, kWave);
                         const uint32_t s_excl = (uint32_t)__shfl(nreg_excl, src, kWave);
@@ -434,7 +416,7 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                             }
                             // the region's first area (w = 0, r = 0)
                             a = mix64(g ^ KA);
-                            X = poisson_fast(pois, a);
+                            X = poisson_fast(C, sPois, a);
                             rest = nau - 1;
                         }
                         const bool push_d = act && X > 0;
@@ -443,27 +425,27 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                         const uint64_t br = __ballot(push_r);
                         if (push_d) {
                             const uint32_t pos = (dq_head + dq_count + rank_in(bd)) & (kCapD - 1);
-                            Q.dq_a[pos] = a;
-                            Q.dq_x[pos] = x;
-                            Q.dq_r[pos] = 0;
-                            Q.dq_w[pos] = 0;
-                            Q.dq_m[pos] = meta | (X << 23);
+                            at<uint64_t>(wb, kOffDqA, pos) = a;
+                            at<double>(wb, kOffDqX, pos) = x;
+                            at<uint32_t>(wb, kOffDqR, pos) = 0;
+                            at<uint32_t>(wb, kOffDqW, pos) = 0;
+                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 23);
                         }
                         if (push_r) {
                             const uint32_t pos = (rq_head + rq_count + rank_in(br)) & (kCapR - 1);
-                            Q.rq_g[pos] = g;
-                            Q.rq_x[pos] = x;
-                            Q.rq_rc[pos] = rcu;
-                            Q.rq_na[pos] = nau;
-                            Q.rq_first[pos] = 1;
-                            Q.rq_m[pos] = meta;
+                            at<uint64_t>(wb, kOffRqG, pos) = g;
+                            at<double>(wb, kOffRqX, pos) = x;
+                            at<uint32_t>(wb, kOffRqRc, pos) = rcu;
+                            at<uint32_t>(wb, kOffRqNa, pos) = nau;
+                            at<uint32_t>(wb, kOffRqFirst, pos) = 1;
+                            at<uint32_t>(wb, kOffRqM, pos) = meta;
                         }
-                        dq_count += (uint32_t)__popcll(bd);
-                        rq_count += (uint32_t)__popcll(br);
-                        // areas added to the region queue: sum of rest in two 16-bit halves
-                        const uint32_t lo = scan_add(rest & 0xffffu), hi = scan_add(rest >> 16);
-                        rq_pending += (uint64_t)uni(lane63(lo)) + ((uint64_t)uni(lane63(hi)) << 16);
-                        reg_done += m;
+                        dq_count = uni(dq_count + (uint32_t)__popcll(bd));
+                        rq_count = uni(rq_count + (uint32_t)__popcll(br));
+                        // areas added to the region queue, each region counted at most 64 times:
+                        // a lower bound that only steers when area rounds run full
+                        rq_pending = uni(rq_pending + lane63(scan_add(rest < 64 ? rest : 64)));
+                        reg_done = uni(reg_done + m);
                         if (wave_any(range)) break;
                         if (reg_done == chunk_total) {
                             chunk += kWave;
@@ -476,7 +458,7 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                 if (wave_any(range)) { status = kSetRange; break; }
                 wave_sync();
                 bool filled = true;
-                for (int j = lane; j < k; j += kWave) filled &= Q.rank_bits[j] != kRankEmpty;
+                for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
                 if (wave_all(filled)) break;
                 tau_prev = tau;
                 phi *= 2.0;
@@ -486,8 +468,8 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
         wave_sync();
         const bool ok = status == kSetOk;
         for (int j = lane; j < k; j += kWave) {
-            const uint64_t s = ok ? Q.sval[j] : ~0ull;
-            const uint64_t rb = ok ? Q.rank_bits[j] : kRankEmpty;
+            const uint64_t s = ok ? bin_s[j] : ~0ull;
+            const uint64_t rb = ok ? bin_rank[j] : kRankEmpty;
             if (out_u32) out_u32[set * k + j] = ok ? (uint32_t)s : 0xFFFFFFFFu;
             if (out_s) out_s[set * k + j] = s;
             if (out_rank) out_rank[set * k + j] = __longlong_as_double((long long)rb);
@@ -496,7 +478,7 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
             const int words = (k + 63) / 64;
             for (int wd = 0; wd < words; ++wd) {
                 const int j = wd * 64 + lane;
-                const bool bit = ok && j < k && (Q.sval[j] & 1ull);
+                const bool bit = ok && j < k && (bin_s[j] & 1ull);
                 const uint64_t word = __ballot(bit);
                 if (lane == 0) out_bits[(int64_t)set * words + wd] = word;
             }
@@ -511,11 +493,11 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 int fast_waves_per_block(int k)
 {
     const size_t per = wave_lds_bytes(k);
-    int w = (int)((65536 - 16 * kTable) / per);
+    int w = (int)((65536 - kTablesBytes) / per);
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-size_t fast_lds_bytes(int k, int waves) { return 16 * kTable + (size_t)waves * wave_lds_bytes(k); }
+size_t fast_lds_bytes(int k, int waves) { return kTablesBytes + (size_t)waves * wave_lds_bytes(k); }
 
 hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
