@@ -162,6 +162,61 @@ dms_status dms_hamming_topk(dms_ctx ctx, const uint64_t* db, int64_t n_db, int32
 dms_status dms_calibrate(dms_ctx ctx, int32_t kind, int32_t iters, int64_t bytes, int32_t blocks,
                          void* a, void* b, double* out_ms);
 
+/*
+ * Serving loop (continuous batching).  A server owns, per batch slot, a HIP
+ * stream, a device arena and pinned staging buffers, and scans a caller-owned,
+ * device-resident database of 1-bit sketches (k = 1024, 16 words per row,
+ * row id = position).  Requests are either DMS_REQ_SKETCH (k minhashes of the
+ * request's set, k in {64, 256, 1024}) or DMS_REQ_SEARCH (the set's 1-bit
+ * k = 1024 sketch, then the topk database rows nearest in Hamming distance,
+ * ascending by (distance, row)).  While a slot is free, the requests that have
+ * arrived are admitted in arrival order as long as the slot's memory budget
+ * (max_batch rows, max_batch_nnz nonzeros) allows; batches of different slots
+ * overlap on the GPU.  A request's result depends only on its own set.
+ */
+#define DMS_REQ_SKETCH 0
+#define DMS_REQ_SEARCH 1
+
+typedef struct {
+    int32_t max_batch;     /* requests per batch slot, 1..4096 */
+    int32_t max_inflight;  /* batch slots (streams) in flight, 1..16 */
+    int64_t max_batch_nnz; /* nonzeros a slot holds (its input arena) */
+    int32_t max_set_nnz;   /* largest request set accepted, <= max_batch_nnz */
+    int32_t db_words;      /* words per database row: 16 */
+    int32_t topk;          /* neighbours per search, 1..64 */
+} dms_server_config;
+
+typedef struct dms_server_s* dms_server;
+
+/* Create a server on ctx (the context must outlive it).  db: device
+ * uint64[n_db*16], owned by the caller, read-only while the server lives.
+ * Errors: DMS_EINVAL, DMS_ENOMEM, DMS_EHIP, DMS_ESPEC. */
+dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, const uint64_t* db,
+                             int64_t n_db, dms_server* out);
+dms_status dms_server_destroy(dms_server s);
+
+/*
+ * Serve n_req requests whose arrival times (seconds after the call starts,
+ * non-decreasing) are given: an open-loop trace replayed in real time; returns
+ * when every request is answered.  All pointers are host memory.
+ *   kind[n_req], k[n_req]               request kind and sketch size
+ *   row_ptr[n_req+1], idx, w            the request sets (CSR)
+ *   sketch_off[n_req], out_sketch       request r's k minhashes go to
+ *                                       out_sketch[sketch_off[r] ...] (NULL: none)
+ *   out_status[n_req]                   DMS_SET_* per request (or NULL)
+ *   out_ids[n_req*topk], out_dist[...]  search results of search requests (or NULL)
+ *   out_latency_s[n_req]                completion minus arrival (or NULL)
+ *   out_stats[7]                        requests/s, p50 s, p99 s, max s, batches,
+ *                                       mean requests per batch, elapsed s (or NULL)
+ * Errors: DMS_EINVAL (a request outside the configured limits, an arrival out
+ * of order), DMS_EHIP, DMS_ESPEC.
+ */
+dms_status dms_server_replay(dms_server s, int64_t n_req, const double* arrival_s,
+                             const int32_t* kind, const int32_t* k, const int64_t* row_ptr,
+                             const int32_t* idx, const double* w, const int64_t* sketch_off,
+                             uint32_t* out_sketch, int8_t* out_status, int64_t* out_ids,
+                             int32_t* out_dist, double* out_latency_s, double* out_stats);
+
 /* Wait until all work queued on the context's stream is done. */
 dms_status dms_sync(dms_ctx ctx);
 

@@ -33,6 +33,11 @@ __global__ void sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_
                                    double* out_rank, double phi0, double phi_max,
                                    unsigned long long* next_set);
 size_t fast_lds_bytes(int k, int waves);
+size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
+int hamming_blocks(int64_t n_db, int n_cu);
+hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
+                          int64_t n_q, int topk, int64_t* out_ids, int32_t* out_dist,
+                          uint64_t* partial, int n_blocks, hipStream_t st);
 hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks,
                      hipStream_t st);
 hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
@@ -46,6 +51,8 @@ struct dms_ctx_s {
     int engine = DMS_ENGINE_FAST;
     int n_cu = 0;
     unsigned long long* counter = nullptr;  // work-stealing cursor of the fast engine
+    void* scratch = nullptr;                 // search partial results, grown on demand
+    size_t scratch_bytes = 0;
     double phi0 = 1.0;
     double lsh_phi0 = 2.0;
     double phi_max = 1048576.0;
@@ -116,6 +123,14 @@ struct DeviceGuard {
 
 }  // namespace
 
+namespace dms {
+int ctx_spec(dms_ctx c, uint32_t t, const SpecTables** out) { return spec_for(c, t, out); }
+int ctx_device(dms_ctx c) { return c->device; }
+int ctx_n_cu(dms_ctx c) { return c->n_cu; }
+double ctx_phi0(dms_ctx c) { return c->phi0; }
+double ctx_phi_max(dms_ctx c) { return c->phi_max; }
+}  // namespace dms
+
 extern "C" {
 
 dms_status dms_create(dms_ctx* out, int device, uint64_t seed)
@@ -146,6 +161,7 @@ dms_status dms_destroy(dms_ctx c)
     DeviceGuard g(c->device);
     for (auto& kv : c->spec) (void)hipFree(kv.second);
     if (c->counter) (void)hipFree(c->counter);
+    if (c->scratch) (void)hipFree(c->scratch);
     delete c;
     return DMS_OK;
 }
@@ -268,8 +284,31 @@ dms_status dms_hamming_topk(dms_ctx c, const uint64_t* db, int64_t n_db, int32_t
                             const uint64_t* queries, int64_t n_q, int32_t topk, int64_t* out_ids,
                             int32_t* out_dist)
 {
-    (void)db; (void)n_db; (void)words; (void)queries; (void)n_q; (void)topk; (void)out_ids; (void)out_dist;
-    return fail(c, DMS_EINVAL, "hamming top-k not available yet");
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (words < 1 || words > 64 || topk < 1 || topk > 64 || n_q < 0 || n_q > 4096 || n_db < 0 ||
+        n_db >= 2147483648LL)
+        return fail(c, DMS_EINVAL, "bad hamming arguments");
+    if (n_q == 0) return DMS_OK;
+    if (!queries || !out_ids || !out_dist || (n_db > 0 && !db)) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    const int blocks = dms::hamming_blocks(n_db, c->n_cu);
+    const size_t need = dms::hamming_partial_bytes(n_q, blocks, topk);
+    if (need > c->scratch_bytes) {
+        // the previous scratch may still be read by queued work on this stream
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+        if (c->scratch) (void)hipFree(c->scratch);
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+        e = hipMalloc(&c->scratch, need);
+        if (e != hipSuccess) return fail(c, DMS_ENOMEM, "hipMalloc(search scratch): %s", hipGetErrorString(e));
+        c->scratch_bytes = need;
+    }
+    hipError_t e = dms::launch_hamming(db, n_db, words, queries, n_q, topk, out_ids, out_dist,
+                                       (uint64_t*)c->scratch, blocks, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hamming launch");
+    return DMS_OK;
 }
 
 dms_status dms_calibrate(dms_ctx c, int32_t kind, int32_t iters, int64_t bytes, int32_t blocks,

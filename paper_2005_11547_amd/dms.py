@@ -20,9 +20,18 @@ FMT_U32, FMT_1BIT = 0, 1
 
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
-           "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate"]
+           "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
+           "dms_server_create", "dms_server_destroy", "dms_server_replay"]
+
+REQ_SKETCH, REQ_SEARCH = 0, 1
 
 _lib = None
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_nnz", ctypes.c_int64), ("max_set_nnz", ctypes.c_int32),
+                ("db_words", ctypes.c_int32), ("topk", ctypes.c_int32)]
 
 
 class DMSError(RuntimeError):
@@ -56,6 +65,9 @@ def lib():
         "dms_t_of_k": ([i32, P(u32)], i32),
         "dms_spec_constants": ([u64, u32, vp, vp, vp, vp, vp], i32),
         "dms_calibrate": ([vp, i32, i32, i64, i32, vp, vp, P(f64)], i32),
+        "dms_server_create": ([vp, P(ServerConfig), vp, i64, P(vp)], i32),
+        "dms_server_destroy": ([vp], i32),
+        "dms_server_replay": ([vp, i64] + [vp] * 13, i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -210,6 +222,63 @@ class Context:
         dist = torch.empty((nq, topk), dtype=torch.int32, device=db.device)
         self.dms_hamming_topk(db, db.shape[0], words, queries, nq, topk, ids, dist)
         return ids, dist
+
+
+class Server:
+    """Continuous-batching serving loop (dms_server_*) over a device-resident
+    database of 1-bit k = 1024 sketches."""
+
+    def __init__(self, ctx: Context, db, topk=10, max_batch=256, max_inflight=4,
+                 max_batch_nnz=1 << 20, max_set_nnz=4096):
+        import numpy as np
+        self.ctx, self.db, self.topk = ctx, db, topk
+        cfg = ServerConfig(max_batch, max_inflight, max_batch_nnz, max_set_nnz, 16, topk)
+        self._h = ctypes.c_void_p()
+        st = lib().dms_server_create(ctx._h, ctypes.byref(cfg), _ptr(db), db.shape[0] if db is not None else 0,
+                                     ctypes.byref(self._h))
+        if st != DMS_OK:
+            raise DMSError(f"dms_server_create: {lib().dms_status_str(st).decode()}")
+        self._np = np
+
+    def close(self):
+        if self._h:
+            lib().dms_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def replay(self, arrival_s, kind, k, row_ptr, idx, w):
+        """Serve a trace; returns dict of per-request results and summary stats."""
+        np = self._np
+        n = len(arrival_s)
+        arrival_s = np.ascontiguousarray(arrival_s, np.float64)
+        kind = np.ascontiguousarray(kind, np.int32)
+        k = np.ascontiguousarray(k, np.int32)
+        row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+        idx = np.ascontiguousarray(idx, np.int32)
+        w = np.ascontiguousarray(w, np.float64)
+        off = np.zeros(n, np.int64)
+        if n:
+            off[1:] = np.cumsum(k[:-1].astype(np.int64))
+        sk = np.zeros(int(k.astype(np.int64).sum()), np.uint32)
+        status = np.zeros(n, np.int8)
+        ids = np.full((n, self.topk), -2, np.int64)
+        dist = np.full((n, self.topk), -2, np.int32)
+        lat = np.zeros(n, np.float64)
+        stats = np.zeros(7, np.float64)
+        st = lib().dms_server_replay(self._h, n, _ptr(arrival_s), _ptr(kind), _ptr(k), _ptr(row_ptr),
+                                     _ptr(idx), _ptr(w), _ptr(off), _ptr(sk), _ptr(status), _ptr(ids),
+                                     _ptr(dist), _ptr(lat), _ptr(stats))
+        if st != DMS_OK:
+            raise DMSError(f"dms_server_replay: {lib().dms_status_str(st).decode()}")
+        sketches = [sk[off[i]:off[i] + k[i]] for i in range(n)]
+        return dict(sketch=sketches, status=status, ids=ids, dist=dist, latency=lat,
+                    stats=dict(req_per_s=stats[0], p50_s=stats[1], p99_s=stats[2], max_s=stats[3],
+                               batches=int(stats[4]), mean_batch=stats[5], elapsed_s=stats[6]))
 
 
 def to_device(row_ptr, idx, w, device="cuda"):

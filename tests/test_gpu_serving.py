@@ -1,0 +1,135 @@
+"""GPU tests of the search kernel and the continuous-batching serving loop,
+through the C ABI, against the oracle (all expected values come from oracle/)."""
+import numpy as np
+import pytest
+
+import workloads as WL
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SEED = WL.HASH_SEED
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2005_11547_amd import Context
+    c = Context(SEED)
+    yield c
+    c.close()
+
+
+def _bits(rng, n, words):
+    return rng.integers(0, 2 ** 63, size=(n, words), dtype=np.int64).view(np.uint64) ^ \
+        (rng.integers(0, 2, size=(n, words), dtype=np.int64).view(np.uint64) << np.uint64(63))
+
+
+@pytest.mark.parametrize("words,n_db,n_q,topk", [(16, 50_000, 40, 10), (1, 3000, 17, 10),
+                                                  (4, 20_000, 33, 64), (16, 5, 3, 10),
+                                                  (16, 1, 1, 1), (7, 9000, 16, 5)])
+def test_hamming_topk_matches_brute_force(torch, ctx, words, n_db, n_q, topk):
+    print(f"[search] words={words} n_db={n_db} n_q={n_q} topk={topk}", flush=True)
+    rng = np.random.default_rng(words * 1000 + n_db)
+    db = _bits(rng, n_db, words)
+    if n_db > 100:
+        db[50:70] = db[10]       # exact duplicates: ties broken by the smaller row id
+        db[80] = ~db[10]
+    q = _bits(rng, n_q, words)
+    q[0] = db[min(10, n_db - 1)]  # a query equal to a database row
+    if n_q > 2 and n_db > 3:
+        q[1] = db[3] ^ np.uint64(1)
+    ids, dist = ctx.hamming_topk(torch.from_numpy(db.view(np.int64)).cuda(),
+                                 torch.from_numpy(q.view(np.int64)).cuda(), topk)
+    torch.cuda.synchronize()
+    ref_ids, ref_dist = O.hamming_topk(db, q, topk)
+    got_ids, got_dist = ids.cpu().numpy(), dist.cpu().numpy()
+    m = min(topk, n_db)
+    assert np.array_equal(got_ids[:, :m], ref_ids[:, :m])
+    assert np.array_equal(got_dist[:, :m], ref_dist[:, :m])
+    assert (got_ids[:, m:] == -1).all() and (got_dist[:, m:] == -1).all()
+
+
+def _trace(rng, n_req, rate):
+    rp, idx, w = WL.serving_sets(rng, n_req)
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    kind = (rng.random(n_req) < 0.5).astype(np.int32)  # 1 = search
+    k = np.where(kind == 1, 1024, rng.choice([64, 256, 1024], size=n_req)).astype(np.int32)
+    return arrival, kind, k, rp, idx, w
+
+
+@pytest.fixture(scope="module")
+def served(torch, ctx):
+    from paper_2005_11547_amd import Server
+    rng = np.random.default_rng(55)
+    n_db = 1500
+    db_rp, db_idx, db_w = WL.serving_sets(rng, n_db)
+    db_bits = O.sketch_csr(db_rp, db_idx, db_w, 1024, SEED)["bits"]   # the oracle builds the database
+    db = torch.from_numpy(db_bits.view(np.int64)).cuda()
+    arrival, kind, k, rp, idx, w = _trace(rng, 240, 20_000.0)
+    srv = Server(ctx, db, topk=10, max_batch=64, max_inflight=3)
+    out = srv.replay(arrival, kind, k, rp, idx, w)
+    return dict(db_bits=db_bits, db=db, trace=(arrival, kind, k, rp, idx, w), out=out, srv=srv)
+
+
+def test_served_results_equal_oracle(served):
+    arrival, kind, k, rp, idx, w = served["trace"]
+    out = served["out"]
+    print(f"[serve] stats {out['stats']}", flush=True)
+    for r in range(len(arrival)):
+        ii, ww = idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]
+        ref = O.sketch_csr(np.array([0, len(ii)]), ii, ww, int(k[r]), SEED)
+        assert out["status"][r] == ref["status"][0]
+        assert np.array_equal(out["sketch"][r], ref["u32"][0]), r
+        if kind[r] == 1:
+            rid, rdist = O.hamming_topk(served["db_bits"], ref["bits"], 10)
+            assert np.array_equal(out["ids"][r], rid[0]) and np.array_equal(out["dist"][r], rdist[0]), r
+        else:
+            assert (out["ids"][r] == -2).all()   # untouched: no search for a sketch request
+    assert out["stats"]["batches"] >= 1 and out["stats"]["p99_s"] >= out["stats"]["p50_s"] > 0
+
+
+def test_each_result_same_alone_and_in_the_mix(served):
+    arrival, kind, k, rp, idx, w = served["trace"]
+    out = served["out"]
+    for r in range(0, len(arrival), 6):
+        sub_rp = np.array([0, rp[r + 1] - rp[r]], np.int64)
+        alone = served["srv"].replay(np.zeros(1), kind[r:r + 1], k[r:r + 1], sub_rp,
+                                     idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]])
+        assert np.array_equal(alone["sketch"][0], out["sketch"][r])
+        assert alone["status"][0] == out["status"][r]
+        assert np.array_equal(alone["ids"][0], out["ids"][r])
+        assert np.array_equal(alone["dist"][0], out["dist"][r])
+
+
+def test_admission_under_a_tiny_arena(torch, ctx, served):
+    from paper_2005_11547_amd import Server
+    arrival, kind, k, rp, idx, w = served["trace"]
+    n = 60
+    srv = Server(ctx, served["db"], topk=10, max_batch=3, max_inflight=2, max_batch_nnz=4096,
+                 max_set_nnz=4096)
+    small = srv.replay(arrival[:n] * 0.0, kind[:n], k[:n], rp[:n + 1], idx[:rp[n]], w[:rp[n]])
+    srv.close()
+    for r in range(n):
+        assert np.array_equal(small["sketch"][r], served["out"]["sketch"][r])
+        assert np.array_equal(small["ids"][r], served["out"]["ids"][r])
+    assert small["stats"]["batches"] >= n / 3
+
+
+def test_server_rejects_bad_requests(torch, ctx, served):
+    from paper_2005_11547_amd import DMSError
+    arrival, kind, k, rp, idx, w = served["trace"]
+    bad_k = k[:2].copy()
+    bad_k[0] = 128
+    with pytest.raises(DMSError):
+        served["srv"].replay(arrival[:2], kind[:2], bad_k, rp[:3], idx[:rp[2]], w[:rp[2]])
+    bad_kind = kind[:2].copy()
+    bad_kind[:] = 1
+    bad_k2 = np.array([64, 64], np.int32)
+    with pytest.raises(DMSError):
+        served["srv"].replay(arrival[:2], bad_kind, bad_k2, rp[:3], idx[:rp[2]], w[:rp[2]])
