@@ -62,6 +62,59 @@ def calibrate_mixer(ctx, torch, n_cu):
     return mixers / (ms * 1e-3)
 
 
+def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
+    """The serving workload: Poisson arrivals at `rate`, half sketch-only requests
+    (k uniform in {64, 256, 1024}), half 1-bit k = 1024 sketch + top-10 Hamming
+    search against a device-resident database of n_db sketched sets; 1% of the
+    searches are near-duplicates (J = 0.9) of database rows.  The first `warm`
+    seconds of the trace are excluded from the latency figures."""
+    from paper_2005_11547_amd import Server, dms
+    rng = np.random.Generator(np.random.PCG64(5))
+    t0 = time.time()
+    db_rp, db_idx, db_w = WL.serving_sets(rng, n_db)
+    log(f"serving: database of {n_db} sets generated in {time.time() - t0:.1f}s")
+    d = [torch.from_numpy(a).cuda() for a in (db_rp, db_idx, db_w)]
+    words = 16
+    db_bits = torch.empty((n_db, words), dtype=torch.int64, device="cuda")
+    st = torch.empty(n_db, dtype=torch.int8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.dms_sketch_csr(n_db, d[0], d[1], d[2], 1024, None, db_bits, st)
+    torch.cuda.synchronize()
+    log(f"serving: database sketched (k=1024, 1-bit) in {time.time() - t0:.2f}s")
+    del d
+    n_req = int(rate * (seconds + warm))
+    rp, idx, w = WL.serving_sets(rng, n_req)
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    kind = (rng.random(n_req) < 0.5).astype(np.int32)
+    k = np.where(kind == 1, 1024, rng.choice([64, 256, 1024], size=n_req)).astype(np.int32)
+    # plant near-duplicates of database rows among the searches
+    planted = np.nonzero(kind == 1)[0]
+    planted = planted[rng.random(len(planted)) < 0.01]
+    targets = rng.integers(0, n_db, size=len(planted))
+    rows = [(idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]) for r in range(n_req)]
+    for r, tgt in zip(planted, targets):
+        rows[r] = WL.near_duplicate(rng, db_idx[db_rp[tgt]:db_rp[tgt + 1]], db_w[db_rp[tgt]:db_rp[tgt + 1]], 0.9)
+    rp, idx, w = WL.csr_from_rows(rows)
+    srv = Server(ctx, db_bits, topk=10, max_batch=512, max_inflight=4, max_batch_nnz=1 << 21,
+                 max_set_nnz=8192)
+    log(f"serving: replaying {n_req} requests at {rate:.0f}/s")
+    out = srv.replay(arrival, kind, k, rp, idx, w)
+    srv.close()
+    steady = arrival >= warm
+    lat = np.sort(out["latency"][steady])
+    top1 = float(np.mean(out["ids"][planted, 0] == targets)) if len(planted) else None
+    res = {"rate_req_s": rate, "requests": int(n_req), "completed_req_s": out["stats"]["req_per_s"],
+           "p50_ms": float(lat[int(0.50 * (len(lat) - 1))] * 1e3),
+           "p99_ms": float(lat[int(0.99 * (len(lat) - 1))] * 1e3),
+           "max_ms": float(lat[-1] * 1e3), "batches": out["stats"]["batches"],
+           "mean_batch": out["stats"]["mean_batch"], "db_rows": n_db,
+           "search_share": float(kind.mean()), "planted_top1": top1,
+           "trace": f"{seconds:.0f}s after {warm:.0f}s warm-up"}
+    log(f"serving: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,8 +124,11 @@ def main():
     ap.add_argument("--engine", default="fast", choices=["fast", "plain"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the oracle CPU baseline (0 disables it)")
-    ap.add_argument("--cpu-stride", type=int, default=250,
+    ap.add_argument("--cpu-stride", type=int, default=25,
                     help="oracle sample: every n-th set")
+    ap.add_argument("--serving-seconds", type=float, default=5.0,
+                    help="length of the served trace at 50k requests/s (0 disables serving)")
+    ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -196,6 +252,8 @@ def main():
                          "sample": f"every {stride}th set of the same batch, first {got} of them "
                                    f"({t_cpu:.1f}s of single-thread CPU work)"},
     }
+    if args.serving_seconds > 0:
+        result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db)
     print(json.dumps(result), flush=True)
 
 
