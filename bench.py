@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
+    ap.add_argument("--copy-calibration", type=int, default=1 << 30,
+                    help="bytes moved by the stream-copy calibration kernel (0 disables it)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -224,6 +226,10 @@ def main():
     achieved = ops_launch / (ms * 1e-3) / 1e12
     hbm_bytes = 8.0 * (n_sets + 1) + 12.0 * nnz + n_sets * (4.0 * k + 8.0 * words + 1.0)
 
+    traffic = None
+    if args.workload == "batch_k256" and args.engine == "fast":
+        from paper_2005_11547_amd import profiling
+        traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", "traffic_sketch_fast_batch_k256.txt"))
     result = {
         "metric": "sketches/sec",
         "value": sets_per_s,
@@ -243,7 +249,7 @@ def main():
                    "k": k, "engine": args.engine, "parallelism": "one GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
                      "unit": "T int32 lane-op/s", "frac": achieved / PEAK_INT_TOPS,
-                     "traffic": None,
+                     "traffic": traffic,
                      "mixers_per_set": float(H[ok].mean()) if ok.any() else 0.0,
                      "lane_ops_per_mixer": c_mix,
                      "hbm_gbs_algorithmic": hbm_bytes / (ms * 1e-3) / 1e9},
@@ -252,6 +258,16 @@ def main():
                          "sample": f"every {stride}th set of the same batch, first {got} of them "
                                    f"({t_cpu:.1f}s of single-thread CPU work)"},
     }
+    if args.copy_calibration > 0:
+        nb = (args.copy_calibration // 16) * 16
+        src = torch.empty(nb // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        ctx.calibrate(2, 1, n_cu * 8, src, dst, nb)  # warm-up
+        ms_copy = min(ctx.calibrate(2, 1, n_cu * 8, src, dst, nb) for _ in range(3))
+        result["roofline"]["hbm_copy_gbs"] = 2.0 * nb / (ms_copy * 1e-3) / 1e9
+        log(f"stream copy of {nb} bytes: {result['roofline']['hbm_copy_gbs']:.0f} GB/s (read+write)")
+        del src, dst
     if args.serving_seconds > 0:
         result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db)
     print(json.dumps(result), flush=True)
