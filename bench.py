@@ -115,6 +115,53 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
     return res
 
 
+def secondary_runs(ctx, torch, steps=3):
+    """Throughput of the other two batch workloads (k = 1024 uneven batching and
+    (L,K) = (64,8) LSH keys), each checked bit for bit on a row sample."""
+    from oracle import oracle as O
+    from paper_2005_11547_amd import to_device
+    res = {}
+    for name, gen, kind in (("uneven_k1024", WL.uneven_k1024, "sketch"),
+                            ("lsh_L64K8", WL.lsh_L64K8, "lsh")):
+        rp, idx, w = gen()
+        n = len(rp) - 1
+        d = to_device(rp, idx, w)
+        if kind == "sketch":
+            out = torch.empty((n, 1024), dtype=torch.int32, device="cuda")
+            bits = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+            st = torch.empty(n, dtype=torch.int8, device="cuda")
+            run = lambda: ctx.dms_sketch_csr(n, d[0], d[1], d[2], 1024, out, bits, st)
+        else:
+            out = torch.empty((n, 64), dtype=torch.int64, device="cuda")
+            st = torch.empty(n, dtype=torch.int8, device="cuda")
+            run = lambda: ctx.dms_lsh_keys(n, d[0], d[1], d[2], 64, 8, out, st)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rows = np.linspace(0, n - 1, 200).astype(np.int64)
+        sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
+        sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
+        sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        if kind == "sketch":
+            ref = O.sketch_csr(sub_rp, sub_idx, sub_w, 1024, WL.HASH_SEED)["u32"]
+            exact = bool(np.array_equal(got.view(np.uint32), ref))
+        else:
+            ref = O.lsh_csr(sub_rp, sub_idx, sub_w, 64, 8, WL.HASH_SEED)["keys"]
+            exact = bool(np.array_equal(got.view(np.uint64), ref))
+        res[name] = {"sets_per_s": n / (ms * 1e-3), "nnz_per_s": float(rp[-1]) / (ms * 1e-3),
+                     "ms_per_step": ms, "n_sets": n, "bit_exact_sample": {"sets_checked": 200, "exact": exact}}
+        log(f"{name}: {res[name]}")
+        del d, out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +176,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
+    ap.add_argument("--secondary", type=int, default=1,
+                    help="also time the k=1024 and LSH workloads (0 disables)")
     ap.add_argument("--copy-calibration", type=int, default=1 << 30,
                     help="bytes moved by the stream-copy calibration kernel (0 disables it)")
     args = ap.parse_args()
@@ -268,6 +317,8 @@ def main():
         result["roofline"]["hbm_copy_gbs"] = 2.0 * nb / (ms_copy * 1e-3) / 1e9
         log(f"stream copy of {nb} bytes: {result['roofline']['hbm_copy_gbs']:.0f} GB/s (read+write)")
         del src, dst
+    if args.secondary and args.workload == "batch_k256":
+        result["secondary"] = secondary_runs(ctx, torch)
     if args.serving_seconds > 0:
         result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db)
     print(json.dumps(result), flush=True)

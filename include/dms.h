@@ -48,7 +48,7 @@ typedef int32_t dms_status;
  * Theorem 1's output is independent of the phi schedule. */
 #define DMS_OPT_ENGINE 0    /* DMS_ENGINE_* */
 #define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1) */
-#define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 2) */
+#define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 3) */
 #define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
 
 /* Formats of dms_jaccard_est. */

@@ -25,14 +25,13 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
                               unsigned long long* counter, int blocks, hipStream_t st);
-int fast_waves_per_block(int k);
-__global__ void sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
-                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
-                                   const double* __restrict__ wts, int k, uint32_t* out_u32,
-                                   uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                                   double* out_rank, double phi0, double phi_max,
-                                   unsigned long long* next_set);
-size_t fast_lds_bytes(int k, int waves);
+int fast_waves(bool lsh, int k, int K);
+size_t fast_lds(bool lsh, int k, int K, int waves);
+const void* fast_kernel_address(bool lsh);
+hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                           const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                           int8_t* out_status, double phi0, double phi_max,
+                           unsigned long long* counter, int blocks, hipStream_t st);
 size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
 int hamming_blocks(int64_t n_db, int n_cu);
 hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
@@ -54,7 +53,7 @@ struct dms_ctx_s {
     void* scratch = nullptr;                 // search partial results, grown on demand
     size_t scratch_bytes = 0;
     double phi0 = 1.0;
-    double lsh_phi0 = 2.0;
+    double lsh_phi0 = 3.0;
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
     std::string err;
@@ -106,6 +105,18 @@ dms_status spec_for(dms_ctx c, uint32_t t, const dms::SpecTables** out)
     c->spec[t] = dev;
     *out = dev;
     return DMS_OK;
+}
+
+// Blocks of the persistent kernel that fit on the device at once.
+int resident_blocks(dms_ctx c, bool lsh, int k, int K)
+{
+    const int waves = dms::fast_waves(lsh, k, K);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(lsh), 64 * waves,
+                                                     dms::fast_lds(lsh, k, K, waves)) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * c->n_cu;
 }
 
 struct DeviceGuard {
@@ -224,19 +235,13 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     hipError_t e;
     // the flattened engine keeps its queues and k buckets in one block's LDS;
     // beyond 64 KiB the plain engine serves the call
-    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds_bytes(k, 1) > 65536) {
+    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(false, k, 1, 1) > 65536) {
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                      out_status, out_s, out_rank, c->phi0, c->phi_max, c->stream);
     } else {
-        const int waves = dms::fast_waves_per_block(k);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(&dms::sketch_fast_kernel), 64 * waves,
-                dms::fast_lds_bytes(k, waves)) != hipSuccess || per_cu < 1)
-            per_cu = 1;
         e = dms::launch_sketch_fast(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits, out_status,
                                     out_s, out_rank, c->phi0, c->phi_max, c->counter,
-                                    per_cu * c->n_cu, c->stream);
+                                    resident_blocks(c, false, k, 1), c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
     return DMS_OK;
@@ -259,8 +264,15 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     const dms::SpecTables* sp = nullptr;
     dms_status st = spec_for(c, (uint32_t)(L * K), &sp);
     if (st != DMS_OK) return st;
-    hipError_t e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
-                                         c->lsh_phi0, c->phi_max, c->stream);
+    hipError_t e;
+    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(true, L, K, 1) > 65536) {
+        e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
+                                  c->lsh_phi0, c->phi_max, c->stream);
+    } else {
+        e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
+                                 c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, true, L, K),
+                                 c->stream);
+    }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");
     return DMS_OK;
 }

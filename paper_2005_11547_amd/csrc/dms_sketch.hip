@@ -107,7 +107,67 @@ constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits
 constexpr uint32_t kQueueBytes = kOffBins;
 constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
 
-__host__ __device__ constexpr size_t wave_lds_bytes(int k) { return kQueueBytes + (size_t)16 * k; }
+// Bytes of the result area after the queues: k bucket minima (minhash) or L
+// sorted lists of K darts plus counts and owner slots (LSH).
+__host__ __device__ constexpr size_t sink_bytes(bool lsh, int k, int K)
+{
+    return lsh ? (size_t)16 * k * K + (size_t)8 * k : (size_t)16 * k;
+}
+__host__ __device__ constexpr size_t wave_lds_bytes(bool lsh, int k, int K)
+{
+    return kQueueBytes + sink_bytes(lsh, k, K);
+}
+
+// (L,K) LSH tables of one wave: table l holds cnt[l] <= K darts sorted by
+// (rank, id hash).  insert_one is run by one lane per table at a time.
+struct LshTables {
+    uint64_t* rank;
+    uint64_t* sval;
+    int32_t* cnt;
+    int32_t* owner;
+    int K;
+
+    __device__ void insert_one(uint32_t l, uint64_t rb, uint64_t s) const
+    {
+        uint64_t* r = rank + (size_t)l * K;
+        uint64_t* v = sval + (size_t)l * K;
+        const int c = cnt[l];
+        int pos = 0;
+        for (int m = 0; m < c; ++m) {
+            if (r[m] == rb && v[m] == s) return;  // the same dart again (repeated element id)
+            pos += (r[m] < rb || (r[m] == rb && v[m] < s)) ? 1 : 0;
+        }
+        if (pos >= K) return;
+        for (int m = (c < K ? c : K - 1); m > pos; --m) {
+            r[m] = r[m - 1];
+            v[m] = v[m - 1];
+        }
+        r[pos] = rb;
+        v[pos] = s;
+        if (c < K) cnt[l] = c + 1;
+    }
+
+    // Called by all 64 lanes; lanes with `has` insert their dart.  Lanes aiming
+    // at the same table take turns (the smallest lane id wins each round);
+    // different tables are filled in parallel.
+    __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s, int lane) const
+    {
+        bool pending = has;
+        while (wave_any(pending)) {
+            if (pending) __hip_atomic_store(&owner[l], 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_sync();
+            if (pending) __hip_atomic_fetch_min(&owner[l], lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_sync();
+            const bool mine = pending &&
+                __hip_atomic_load(&owner[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
+            if (mine) {
+                insert_one(l, rb, s);
+                pending = false;
+            }
+            wave_sync();
+        }
+    }
+};
 
 template <class T>
 __device__ __forceinline__ T& at(unsigned char* base, uint32_t off, uint32_t i)
@@ -130,14 +190,16 @@ __device__ __forceinline__ double exact_count(double base, double step, double b
 
 }  // namespace
 
-// Persistent flattened DartMinHash; each wave repeatedly takes the next set
-// index from *next_set.
+// Persistent flattened DartMinHash (LSH = false: k buckets keep their
+// minimum) or (L,K) LSH (LSH = true: k = L tables keep their K smallest darts).
+// Each wave repeatedly takes the next set index from *next_set.
+template <bool LSH>
 __global__ void __launch_bounds__(256)
-sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
-                   const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
-                   const double* __restrict__ wts, int k, uint32_t* out_u32, uint64_t* out_bits,
-                   int8_t* out_status, uint64_t* out_s, double* out_rank, double phi0,
-                   double phi_max, unsigned long long* next_set)
+fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __restrict__ rp,
+            const int32_t* __restrict__ idx, const double* __restrict__ wts, int k, int K,
+            uint32_t* out_u32, uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+            double* out_rank, uint64_t* out_keys, double phi0, double phi_max,
+            unsigned long long* next_set)
 {
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
@@ -155,9 +217,15 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(k);
+    unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(LSH, k, K);
     uint64_t* const bin_rank = reinterpret_cast<uint64_t*>(wb + kOffBins);
-    uint64_t* const bin_s = bin_rank + k;
+    uint64_t* const bin_s = bin_rank + (LSH ? k * K : k);
+    LshTables T;
+    T.rank = bin_rank;
+    T.sval = bin_s;
+    T.cnt = reinterpret_cast<int32_t*>(bin_s + k * K);
+    T.owner = T.cnt + k;
+    T.K = K;
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
     const double u = sp->u;
@@ -173,9 +241,13 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
         const RowInfo ri = scan_row(wts, b0, b1, lane);
         int8_t status = ri.status;
         if (status == kSetOk) {
-            for (int j = lane; j < k; j += kWave) {
-                bin_rank[j] = kRankEmpty;
-                bin_s[j] = ~0ull;
+            if (LSH) {
+                for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
+            } else {
+                for (int j = lane; j < k; j += kWave) {
+                    bin_rank[j] = kRankEmpty;
+                    bin_s[j] = ~0ull;
+                }
             }
             double phi = phi0;
             double tau_prev = -1.0;  // darts of rank <= tau_prev are already in the buckets
@@ -245,8 +317,12 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                         const uint64_t j = (meta >> 18) & 31;
                         const double V = unit53(mix64(a ^ KV ^ j));
                         const double weight = sW[nu] + ((double)wv + V) * ldexp(u, nu - rho);
-                        if ((uint32_t)lane < m && weight <= xi) {
-                            const uint64_t s = mix64(a ^ KS ^ j);
+                        const bool acc = (uint32_t)lane < m && weight <= xi;
+                        uint64_t s = 0;
+                        if (acc) s = mix64(a ^ KS ^ j);
+                        if (LSH) {
+                            T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, lane);
+                        } else if (acc) {
                             bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
                         }
                         pq_head = uni((pq_head + m) & (kCapP - 1));
@@ -458,7 +534,11 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                 if (wave_any(range)) { status = kSetRange; break; }
                 wave_sync();
                 bool filled = true;
-                for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
+                if (LSH) {
+                    for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
+                } else {
+                    for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
+                }
                 if (wave_all(filled)) break;
                 tau_prev = tau;
                 phi *= 2.0;
@@ -467,20 +547,32 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
         // outputs
         wave_sync();
         const bool ok = status == kSetOk;
-        for (int j = lane; j < k; j += kWave) {
-            const uint64_t s = ok ? bin_s[j] : ~0ull;
-            const uint64_t rb = ok ? bin_rank[j] : kRankEmpty;
-            if (out_u32) out_u32[set * k + j] = ok ? (uint32_t)s : 0xFFFFFFFFu;
-            if (out_s) out_s[set * k + j] = s;
-            if (out_rank) out_rank[set * k + j] = __longlong_as_double((long long)rb);
-        }
-        if (out_bits) {
-            const int words = (k + 63) / 64;
-            for (int wd = 0; wd < words; ++wd) {
-                const int j = wd * 64 + lane;
-                const bool bit = ok && j < k && (bin_s[j] & 1ull);
-                const uint64_t word = __ballot(bit);
-                if (lane == 0) out_bits[(int64_t)set * words + wd] = word;
+        if (LSH) {
+            // table l's key folds its K ordered dart ids
+            for (int l = lane; l < k; l += kWave) {
+                uint64_t h = 0;
+                if (ok) {
+                    h = mix64(sp->key_l ^ (uint64_t)l);
+                    for (int m2 = 0; m2 < K; ++m2) h = mix64(h ^ T.sval[(size_t)l * K + m2]);
+                }
+                out_keys[set * k + l] = h;
+            }
+        } else {
+            for (int j = lane; j < k; j += kWave) {
+                const uint64_t s = ok ? bin_s[j] : ~0ull;
+                const uint64_t rb = ok ? bin_rank[j] : kRankEmpty;
+                if (out_u32) out_u32[set * k + j] = ok ? (uint32_t)s : 0xFFFFFFFFu;
+                if (out_s) out_s[set * k + j] = s;
+                if (out_rank) out_rank[set * k + j] = __longlong_as_double((long long)rb);
+            }
+            if (out_bits) {
+                const int words = (k + 63) / 64;
+                for (int wd = 0; wd < words; ++wd) {
+                    const int j = wd * 64 + lane;
+                    const bool bit = ok && j < k && (bin_s[j] & 1ull);
+                    const uint64_t word = __ballot(bit);
+                    if (lane == 0) out_bits[(int64_t)set * words + wd] = word;
+                }
             }
         }
         if (out_status && lane == 0) out_status[set] = status;
@@ -490,14 +582,36 @@ sketch_fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
 
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
-int fast_waves_per_block(int k)
+// Explicit instantiations: the host launches both.
+template __global__ void fast_kernel<false>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
+                                            const double*, int, int, uint32_t*, uint64_t*, int8_t*,
+                                            uint64_t*, double*, uint64_t*, double, double,
+                                            unsigned long long*);
+template __global__ void fast_kernel<true>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
+                                           const double*, int, int, uint32_t*, uint64_t*, int8_t*,
+                                           uint64_t*, double*, uint64_t*, double, double,
+                                           unsigned long long*);
+
+int fast_waves(bool lsh, int k, int K)
 {
-    const size_t per = wave_lds_bytes(k);
+    const size_t per = wave_lds_bytes(lsh, k, K);
     int w = (int)((65536 - kTablesBytes) / per);
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-size_t fast_lds_bytes(int k, int waves) { return kTablesBytes + (size_t)waves * wave_lds_bytes(k); }
+size_t fast_lds(bool lsh, int k, int K, int waves)
+{
+    return kTablesBytes + (size_t)waves * wave_lds_bytes(lsh, k, K);
+}
+
+int fast_waves_per_block(int k) { return fast_waves(false, k, 1); }
+size_t fast_lds_bytes(int k, int waves) { return fast_lds(false, k, 1, waves); }
+
+const void* fast_kernel_address(bool lsh)
+{
+    return lsh ? reinterpret_cast<const void*>(&fast_kernel<true>)
+               : reinterpret_cast<const void*>(&fast_kernel<false>);
+}
 
 hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
@@ -506,14 +620,31 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               unsigned long long* counter, int blocks, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves_per_block(k);
-    const size_t lds = fast_lds_bytes(k, waves);
+    const int waves = fast_waves(false, k, 1);
+    const size_t lds = fast_lds(false, k, 1, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(sketch_fast_kernel, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
-                       n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s, out_rank, phi0,
-                       phi_max, counter);
+    hipLaunchKernelGGL(fast_kernel<false>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+                       n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
+                       (uint64_t*)nullptr, phi0, phi_max, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                           const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                           int8_t* out_status, double phi0, double phi_max,
+                           unsigned long long* counter, int blocks, hipStream_t st)
+{
+    if (n_sets <= 0) return hipSuccess;
+    const int waves = fast_waves(true, L, K);
+    const size_t lds = fast_lds(true, L, K, waves);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    const int64_t need = (n_sets + waves - 1) / waves;
+    if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
+    hipLaunchKernelGGL(fast_kernel<true>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+                       n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
+                       (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter);
     return hipGetLastError();
 }
 
