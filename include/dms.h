@@ -50,6 +50,10 @@ typedef int32_t dms_status;
 #define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1) */
 #define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 3) */
 #define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
+#define DMS_OPT_SPLIT_NNZ 4 /* fast engine: sets with more nonzeros are shared by several
+                               wavefronts, one part of at most this many nonzeros each
+                               (default 4096; 0 disables).  The call then reads two counts back
+                               from the device before its main launch. */
 
 /* Formats of dms_jaccard_est. */
 #define DMS_FMT_U32 0  /* k uint32 minhash values per set */

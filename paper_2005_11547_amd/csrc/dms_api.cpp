@@ -28,6 +28,20 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
 int fast_waves(bool lsh, int k, int K);
 size_t fast_lds(bool lsh, int k, int K, int waves);
 const void* fast_kernel_address(bool lsh);
+hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                                    double* out_rank, double phi0, double phi_max,
+                                    unsigned long long* counter, int blocks, const void* parts,
+                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
+                                    hipStream_t st);
+size_t plan_part_bytes();
+size_t plan_heavy_bytes();
+hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
+                             unsigned long long* plan, hipStream_t st);
+hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
+                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
+                            hipStream_t st);
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
@@ -52,6 +66,14 @@ struct dms_ctx_s {
     unsigned long long* counter = nullptr;  // work-stealing cursor of the fast engine
     void* scratch = nullptr;                 // search partial results, grown on demand
     size_t scratch_bytes = 0;
+    double split_nnz = 4096;                 // sets with more nonzeros are cut into parts
+    unsigned long long* plan = nullptr;      // planning counters of the fast engine
+    void* parts = nullptr;                   // part descriptors, heavy sets, partial buckets
+    size_t parts_bytes = 0;
+    void* heavy = nullptr;
+    size_t heavy_bytes = 0;
+    uint64_t* partial = nullptr;
+    size_t partial_bytes = 0;
     double phi0 = 1.0;
     double lsh_phi0 = 3.0;
     double phi_max = 1048576.0;
@@ -107,6 +129,21 @@ dms_status spec_for(dms_ctx c, uint32_t t, const dms::SpecTables** out)
     return DMS_OK;
 }
 
+// Make *buf hold at least `need` bytes of device memory (contents not kept).
+// The stream has been synchronised by the caller.
+dms_status grow(dms_ctx c, void** buf, size_t* have, size_t need)
+{
+    if (need <= *have) return DMS_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
+    const size_t bytes = need + need / 4 + 256;
+    hipError_t e = hipMalloc(buf, bytes);
+    if (e != hipSuccess) return fail(c, DMS_ENOMEM, "hipMalloc(%zu bytes of sketch scratch): %s", bytes, hipGetErrorString(e));
+    *have = bytes;
+    return DMS_OK;
+}
+
 // Blocks of the persistent kernel that fit on the device at once.
 int resident_blocks(dms_ctx c, bool lsh, int k, int K)
 {
@@ -157,7 +194,8 @@ dms_status dms_create(dms_ctx* out, int device, uint64_t seed)
     DeviceGuard g(device);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
-        hipMalloc((void**)&c->counter, 64) != hipSuccess) {
+        hipMalloc((void**)&c->counter, 64) != hipSuccess ||
+        hipMalloc((void**)&c->plan, 64) != hipSuccess) {
         delete c;
         return DMS_EHIP;
     }
@@ -173,6 +211,10 @@ dms_status dms_destroy(dms_ctx c)
     for (auto& kv : c->spec) (void)hipFree(kv.second);
     if (c->counter) (void)hipFree(c->counter);
     if (c->scratch) (void)hipFree(c->scratch);
+    if (c->plan) (void)hipFree(c->plan);
+    if (c->parts) (void)hipFree(c->parts);
+    if (c->heavy) (void)hipFree(c->heavy);
+    if (c->partial) (void)hipFree(c->partial);
     delete c;
     return DMS_OK;
 }
@@ -192,6 +234,11 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
         if (v != DMS_ENGINE_FAST && v != DMS_ENGINE_PLAIN)
             return fail(c, DMS_EINVAL, "unknown engine %g", v);
         c->engine = (int)v;
+        return DMS_OK;
+    case DMS_OPT_SPLIT_NNZ:
+        if (!(v >= 0.0) || v > 1e12 || v != (double)(int64_t)v)
+            return fail(c, DMS_EINVAL, "split threshold must be a non-negative integer");
+        c->split_nnz = v;
         return DMS_OK;
     case DMS_OPT_PHI0:
     case DMS_OPT_LSH_PHI0:
@@ -214,6 +261,7 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_PHI0: *v = c->phi0; return DMS_OK;
     case DMS_OPT_LSH_PHI0: *v = c->lsh_phi0; return DMS_OK;
     case DMS_OPT_PHI_MAX: *v = c->phi_max; return DMS_OK;
+    case DMS_OPT_SPLIT_NNZ: *v = c->split_nnz; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
     }
 }
@@ -239,9 +287,33 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                      out_status, out_s, out_rank, c->phi0, c->phi_max, c->stream);
     } else {
-        e = dms::launch_sketch_fast(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits, out_status,
-                                    out_s, out_rank, c->phi0, c->phi_max, c->counter,
-                                    resident_blocks(c, false, k, 1), c->stream);
+        const int64_t split = (int64_t)c->split_nnz;
+        int64_t n_parts = 0;
+        if (split > 0) {
+            // count the parts of the sets above the threshold, size the scratch, fill the plan
+            unsigned long long counts[2] = {0, 0};
+            e = dms::launch_plan_count(n_sets, row_ptr, split, c->plan, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(counts, c->plan, sizeof counts, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "sketch planning");
+            const int64_t n_heavy = (int64_t)counts[0];
+            n_parts = (int64_t)counts[1];
+            if (n_parts > 0) {
+                dms_status g2 = grow(c, &c->parts, &c->parts_bytes, (size_t)n_parts * dms::plan_part_bytes());
+                if (g2 == DMS_OK) g2 = grow(c, &c->heavy, &c->heavy_bytes, (size_t)n_heavy * dms::plan_heavy_bytes());
+                if (g2 == DMS_OK)
+                    g2 = grow(c, (void**)&c->partial, &c->partial_bytes, (size_t)n_parts * 16 * (size_t)k);
+                if (g2 != DMS_OK) return g2;
+                e = dms::launch_plan_fill(n_sets, row_ptr, w, split, n_heavy, c->plan, c->parts,
+                                          c->heavy, c->stream);
+                if (e != hipSuccess) return hip_fail(c, e, "sketch planning");
+            }
+        }
+        e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
+                                          out_status, out_s, out_rank, c->phi0, c->phi_max,
+                                          c->counter, resident_blocks(c, false, k, 1), c->parts,
+                                          n_parts, c->heavy, c->partial, split, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
     return DMS_OK;

@@ -190,6 +190,27 @@ __device__ __forceinline__ double exact_count(double base, double step, double b
 
 }  // namespace
 
+// A set with more nonzeros than the split threshold is cut into parts of at
+// most `split` consecutive nonzeros.  Every part runs one phi pass over its
+// elements into buckets of its own (in HBM); the part that finishes last
+// merges them by the exact (rank, id) minimum and, if a bucket is still empty,
+// carries on with the doubling retry over the whole set.  Minimum is
+// associative and idempotent, so the result equals the one-wave result.
+struct HeavySet {
+    double sum;      // ||x||_1 of the set (positive weights)
+    int64_t set;
+    int64_t base;    // index of its first part
+    int32_t parts;
+    int32_t done;    // parts finished
+    int32_t range;   // a part met an out-of-range index
+    int32_t status;  // status of the row scan
+};
+struct Part {
+    int64_t set;
+    int32_t heavy;
+    int32_t index;
+};
+
 // Persistent flattened DartMinHash (LSH = false: k buckets keep their
 // minimum) or (L,K) LSH (LSH = true: k = L tables keep their K smallest darts).
 // Each wave repeatedly takes the next set index from *next_set.
@@ -199,7 +220,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             const int32_t* __restrict__ idx, const double* __restrict__ wts, int k, int K,
             uint32_t* out_u32, uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
             double* out_rank, uint64_t* out_keys, double phi0, double phi_max,
-            unsigned long long* next_set)
+            unsigned long long* next_set, const Part* __restrict__ parts, int64_t n_parts,
+            HeavySet* heavy, uint64_t* partial, int64_t split)
 {
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
@@ -231,36 +253,23 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     const double u = sp->u;
     const double td = (double)sp->t;
 
-    for (;;) {
-        unsigned long long got = 0;
-        if (lane == 0) got = atomicAdd(next_set, 1ull);
-        const int64_t set = (int64_t)__shfl(got, 0, kWave);
-        if (set >= n_sets) break;
-
-        const int64_t b0 = rp[set], b1 = rp[set + 1];
-        const RowInfo ri = scan_row(wts, b0, b1, lane);
-        int8_t status = ri.status;
-        if (status == kSetOk) {
-            if (LSH) {
-                for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
-            } else {
-                for (int j = lane; j < k; j += kWave) {
-                    bin_rank[j] = kRankEmpty;
-                    bin_s[j] = ~0ull;
-                }
-            }
-            double phi = phi0;
-            double tau_prev = -1.0;  // darts of rank <= tau_prev are already in the buckets
+    // Runs phi passes over the elements [lo, hi) of a row with ||x||_1 = S,
+    // starting at phi (darts of rank <= tau_prev are already in the buckets),
+    // until no bucket is empty -- or just one pass when `single`.  Returns the
+    // set's status (kSetOk or kSetRange).
+    auto run = [&](int64_t lo, int64_t hi, double S, double phi, double tau_prev, bool single) -> int8_t {
+        int8_t status = kSetOk;
             for (;;) {
                 if (phi > phi_max) { status = kSetRange; break; }
-                const double tau = phi / ri.sum;
+                const double tau = phi / S;
                 // rho runs over 0 .. B1-1: the rows whose lower corner is <= tau
                 int B1 = 0;
                 while (B1 < kTable && sR[B1] <= tau) ++B1;
                 bool range = B1 >= kTable;
                 const float inv_b1 = 1.0f / (float)B1;
 
-                int64_t chunk = b0;        // first element of the current chunk
+                const int64_t b1 = hi;
+                int64_t chunk = lo;        // first element of the current chunk
                 uint32_t chunk_total = 0;  // regions of the chunk
                 uint32_t reg_done = 0;     // regions of the chunk already expanded
                 double ex = 0.0;           // this lane's element weight
@@ -533,6 +542,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 }
                 if (wave_any(range)) { status = kSetRange; break; }
                 wave_sync();
+                if (single) break;
                 bool filled = true;
                 if (LSH) {
                     for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
@@ -542,6 +552,85 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 if (wave_all(filled)) break;
                 tau_prev = tau;
                 phi *= 2.0;
+            }
+        return status;
+    };
+
+    auto clear_buckets = [&]() {
+        if (LSH) {
+            for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
+        } else {
+            for (int j = lane; j < k; j += kWave) {
+                bin_rank[j] = kRankEmpty;
+                bin_s[j] = ~0ull;
+            }
+        }
+    };
+
+    for (;;) {
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(next_set, 1ull);
+        const int64_t item = (int64_t)__shfl(got, 0, kWave);
+        if (item >= n_parts + n_sets) break;
+        int64_t set;
+        int8_t status;
+        if (!LSH && item < n_parts) {
+            // ---- one part of a heavy set ----
+            const Part pt = parts[item];
+            HeavySet* hs = heavy + pt.heavy;
+            set = pt.set;
+            const int64_t b0 = rp[set], b1 = rp[set + 1];
+            const int64_t lo = b0 + (int64_t)pt.index * split;
+            const int64_t hi = lo + split < b1 ? lo + split : b1;
+            const double S = hs->sum;
+            status = (int8_t)hs->status;
+            uint64_t* mine = partial + (size_t)(hs->base + pt.index) * 2 * k;
+            if (status == kSetOk) {
+                clear_buckets();
+                if (run(lo, hi, S, phi0, -1.0, true) == kSetRange && lane == 0) atomicOr(&hs->range, 1);
+                wave_sync();
+                for (int j = lane; j < k; j += kWave) {
+                    mine[j] = bin_rank[j];
+                    mine[k + j] = bin_s[j];
+                }
+            }
+            __threadfence();  // the buckets are visible before the part counts as done
+            int last = 0;
+            if (lane == 0) last = atomicAdd(&hs->done, 1) == hs->parts - 1;
+            if (!__shfl(last, 0, kWave)) continue;
+            __threadfence();
+            if (status == kSetOk && __hip_atomic_load(&hs->range, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                status = kSetRange;
+            if (status == kSetOk) {
+                // merge the parts' buckets, then finish the retry over the whole set
+                const uint64_t* first = partial + (size_t)hs->base * 2 * k;
+                for (int j = lane; j < k; j += kWave) {
+                    uint64_t br = kRankEmpty, bs = ~0ull;
+                    for (int q = 0; q < hs->parts; ++q) {
+                        const uint64_t r = __builtin_nontemporal_load(first + (size_t)q * 2 * k + j);
+                        const uint64_t v = __builtin_nontemporal_load(first + (size_t)q * 2 * k + k + j);
+                        if (r < br || (r == br && v < bs)) {
+                            br = r;
+                            bs = v;
+                        }
+                    }
+                    bin_rank[j] = br;
+                    bin_s[j] = bs;
+                }
+                wave_sync();
+                bool filled = true;
+                for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
+                if (!wave_all(filled)) status = run(b0, b1, S, 2.0 * phi0, phi0 / S, false);
+            }
+        } else {
+            set = item - n_parts;
+            const int64_t b0 = rp[set], b1 = rp[set + 1];
+            if (!LSH && split > 0 && b1 - b0 > split) continue;  // served by its parts
+            const RowInfo ri = scan_row(wts, b0, b1, lane);
+            status = ri.status;
+            if (status == kSetOk) {
+                clear_buckets();
+                status = run(b0, b1, ri.sum, phi0, -1.0, false);
             }
         }
         // outputs
@@ -586,11 +675,101 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 template __global__ void fast_kernel<false>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
                                             const double*, int, int, uint32_t*, uint64_t*, int8_t*,
                                             uint64_t*, double*, uint64_t*, double, double,
-                                            unsigned long long*);
+                                            unsigned long long*, const Part*, int64_t, HeavySet*,
+                                            uint64_t*, int64_t);
 template __global__ void fast_kernel<true>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
                                            const double*, int, int, uint32_t*, uint64_t*, int8_t*,
                                            uint64_t*, double*, uint64_t*, double, double,
-                                           unsigned long long*);
+                                           unsigned long long*, const Part*, int64_t, HeavySet*,
+                                           uint64_t*, int64_t);
+
+// Planning.  plan[0] = heavy sets, plan[1] = parts (counting pass); plan[2],
+// plan[3] are the cursors of the filling pass.
+__global__ void __launch_bounds__(256)
+plan_count_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split,
+                  unsigned long long* plan)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sets) return;
+    const int64_t nnz = rp[s + 1] - rp[s];
+    if (nnz > split) {
+        atomicAdd(&plan[0], 1ull);
+        atomicAdd(&plan[1], (unsigned long long)((nnz + split - 1) / split));
+    }
+}
+
+__global__ void __launch_bounds__(256)
+plan_fill_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split,
+                 unsigned long long* plan, Part* parts, HeavySet* heavy)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sets) return;
+    const int64_t nnz = rp[s + 1] - rp[s];
+    if (nnz <= split) return;
+    const int32_t P = (int32_t)((nnz + split - 1) / split);
+    const int32_t h = (int32_t)atomicAdd(&plan[2], 1ull);
+    const int64_t base = (int64_t)atomicAdd(&plan[3], (unsigned long long)P);
+    HeavySet hs;
+    hs.sum = 0.0;
+    hs.set = s;
+    hs.base = base;
+    hs.parts = P;
+    hs.done = 0;
+    hs.range = 0;
+    hs.status = kSetOk;
+    heavy[h] = hs;
+    for (int32_t p = 0; p < P; ++p) {
+        Part pt;
+        pt.set = s;
+        pt.heavy = h;
+        pt.index = p;
+        parts[base + p] = pt;
+    }
+}
+
+// One wave per heavy set: validity and ||x||_1 of the whole row.
+__global__ void __launch_bounds__(256)
+heavy_scan_kernel(int64_t n_heavy, const int64_t* __restrict__ rp, const double* __restrict__ w,
+                  HeavySet* heavy)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t h = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (h >= n_heavy) return;
+    const int64_t s = heavy[h].set;
+    const RowInfo ri = scan_row(w, rp[s], rp[s + 1], lane);
+    if (lane == 0) {
+        heavy[h].sum = ri.sum;
+        heavy[h].status = ri.status;
+    }
+}
+
+__global__ void reset_plan_kernel(unsigned long long* plan)
+{
+    if (threadIdx.x < 8) plan[threadIdx.x] = 0ull;
+}
+
+size_t plan_part_bytes() { return sizeof(Part); }
+size_t plan_heavy_bytes() { return sizeof(HeavySet); }
+
+hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
+                             unsigned long long* plan, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_plan_kernel, dim3(1), dim3(64), 0, st, plan);
+    hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st,
+                       n_sets, rp, split, plan);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
+                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(plan_fill_kernel, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st,
+                       n_sets, rp, split, plan, (Part*)parts, (HeavySet*)heavy);
+    hipLaunchKernelGGL(heavy_scan_kernel, dim3((unsigned)((n_heavy + 3) / 4)), dim3(256), 0, st,
+                       n_heavy, rp, w, (HeavySet*)heavy);
+    return hipGetLastError();
+}
 
 int fast_waves(bool lsh, int k, int K)
 {
@@ -613,22 +792,36 @@ const void* fast_kernel_address(bool lsh)
                : reinterpret_cast<const void*>(&fast_kernel<false>);
 }
 
+hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                                    double* out_rank, double phi0, double phi_max,
+                                    unsigned long long* counter, int blocks, const void* parts,
+                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
+                                    hipStream_t st)
+{
+    if (n_sets <= 0) return hipSuccess;
+    const int waves = fast_waves(false, k, 1);
+    const size_t lds = fast_lds(false, k, 1, waves);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    const int64_t need = (n_parts + n_sets + waves - 1) / waves;
+    if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
+    hipLaunchKernelGGL(fast_kernel<false>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+                       n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
+                       (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
+                       (HeavySet*)heavy, partial, split);
+    return hipGetLastError();
+}
+
 hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
                               unsigned long long* counter, int blocks, hipStream_t st)
 {
-    if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves(false, k, 1);
-    const size_t lds = fast_lds(false, k, 1, waves);
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-    const int64_t need = (n_sets + waves - 1) / waves;
-    if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<false>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
-                       n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
-                       (uint64_t*)nullptr, phi0, phi_max, counter);
-    return hipGetLastError();
+    return launch_sketch_fast_split(sp, n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s,
+                                    out_rank, phi0, phi_max, counter, blocks, nullptr, 0, nullptr,
+                                    nullptr, 0, st);
 }
 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
@@ -644,7 +837,9 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
     hipLaunchKernelGGL(fast_kernel<true>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
-                       (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter);
+                       (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
+                       (const Part*)nullptr, (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr,
+                       (int64_t)0);
     return hipGetLastError();
 }
 

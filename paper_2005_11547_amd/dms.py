@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdms.so")
 DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
 SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
-OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX = 0, 1, 2, 3
+OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ = 0, 1, 2, 3, 4
 FMT_U32, FMT_1BIT = 0, 1
 
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",

@@ -155,3 +155,23 @@ def test_invalid_arguments(torch, ctx):
         ctx.sketch(rp, idx, w, 5000)
     with pytest.raises(DMSError):
         ctx.lsh(rp, idx, w, 0, 8)
+
+
+@pytest.mark.parametrize("split", [1, 7, 64, 300])
+def test_heavy_sets_cut_into_parts(torch, split):
+    # Sets above the split threshold are shared by several wavefronts and merged
+    # by the last one; the result may not depend on the cut.
+    from paper_2005_11547_amd import Context, dms
+    rp, idx, w = WL.batch_k256(seed=21, n_sets=30)
+    extra = [([5, 9], [0.0, 0.0]), ([1, 2, 3], [0.5, -1.0, 2.0]), ([7], [2.0 ** 300]),
+             ([4, 4, 9, 9, 11], [0.3, 0.7, 1.0, 0.2, 0.5]),
+             (list(range(1000)), [0.0] * 500 + [1.0] * 500)]
+    rows = [(idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]) for r in range(len(rp) - 1)] + extra
+    rp2, idx2, w2 = WL.csr_from_rows(rows)
+    for phi0 in (1.0, 2.0 ** -10):
+        c = Context(SEED, engine=dms.ENGINE_FAST)
+        c.set_option(dms.OPT_SPLIT_NNZ, split)
+        c.set_option(dms.OPT_PHI0, phi0)
+        for k in (1, 100, 256):
+            _check_sketch(torch, c, rp2, idx2, w2, k, f"split={split} phi0={phi0} k={k}")
+        c.close()
