@@ -162,6 +162,57 @@ def secondary_runs(ctx, torch, steps=3):
     return res
 
 
+# The paper's Table 1 (DartMinHash column, mean ms per set on an Intel i7-10510U,
+# one core): (k, ||x||_0, ||x||_1, ms).
+TABLE1 = [(1, 256, 1.0, 0.02), (256, 256, 1.0, 0.17), (4096, 256, 1.0, 2.67), (1, 4096, 1.0, 0.30),
+          (256, 4096, 1.0, 0.49), (4096, 4096, 1.0, 3.64), (64, 64, 1.0, 0.04), (64, 1024, 1.0, 0.10),
+          (64, 16384, 1.0, 1.37), (1024, 64, 1.0, 0.58), (1024, 1024, 1.0, 0.78),
+          (1024, 16384, 1.0, 2.06), (256, 1024, 1.0, 0.26), (256, 1024, 2.0 ** 64, 2.47),
+          (256, 1024, 2.0 ** -64, 2.25), (256, 1024, 2.0 ** 512, 18.58), (256, 1024, 2.0 ** -512, 17.10)]
+
+
+def table1_run(ctx, torch, cpu_seconds=2.0):
+    """The paper's Table 1 shapes: weights uniform on the simplex scaled to ||x||_1,
+    random ids (Section 4, "Synthetic data").  GPU: sets/s on a batch of each
+    shape; oracle: ms per set on one host core; paper: its ms per set (context)."""
+    from oracle import oracle as O
+    from paper_2005_11547_amd import to_device
+    rows = []
+    for i, (k, l0, l1, paper_ms) in enumerate(TABLE1):
+        n = max(200, min(20000, 4_000_000 // l0))
+        rp, idx, w = WL.simplex_sets(100 + i, n, l0, l1)
+        d = to_device(rp, idx, w)
+        out = torch.empty((n, k), dtype=torch.int32, device="cuda")
+        st = torch.empty(n, dtype=torch.int8, device="cuda")
+        ctx.dms_sketch_csr(n, d[0], d[1], d[2], k, out, None, st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.dms_sketch_csr(n, d[0], d[1], d[2], k, out, None, st)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu_ms = e0.elapsed_time(e1)
+        # oracle: sets one by one until the time budget, checked against the GPU
+        t0 = time.perf_counter()
+        m = 0
+        exact = True
+        got = out.cpu().numpy().view(np.uint32)
+        while m < n and time.perf_counter() - t0 < cpu_seconds:
+            r = O.sketch_csr(np.array([0, l0]), idx[rp[m]:rp[m + 1]], w[rp[m]:rp[m + 1]], k, WL.HASH_SEED)
+            exact &= bool(np.array_equal(r["u32"][0], got[m]))
+            m += 1
+        cpu_ms = (time.perf_counter() - t0) / max(m, 1) * 1e3
+        row = {"k": k, "l0": l0, "l1": "2^%d" % round(np.log2(l1)) if l1 != 1.0 else 1,
+               "gpu_sets_per_s": n / (gpu_ms * 1e-3), "gpu_us_per_set": gpu_ms * 1e3 / n,
+               "oracle_ms_per_set": cpu_ms, "paper_ms_per_set": paper_ms,
+               "gpu_batch": n, "bit_exact_sets": m, "exact": exact,
+               "status_ok": bool((st.cpu().numpy() == 0).all())}
+        log(f"table1: {row}")
+        rows.append(row)
+        del d, out
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +227,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
+    ap.add_argument("--table1", action="store_true",
+                    help="time the paper's Table 1 shapes instead (GPU, oracle, paper) and exit")
     ap.add_argument("--secondary", type=int, default=1,
                     help="also time the k=1024 and LSH workloads (0 disables)")
     ap.add_argument("--copy-calibration", type=int, default=1 << 30,
@@ -190,6 +243,11 @@ def main():
 
     import torch
     from paper_2005_11547_amd import Context, dms, to_device
+
+    if args.table1:
+        ctx = Context(WL.HASH_SEED)
+        print(json.dumps({"table1": table1_run(ctx, torch)}), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     k = wl["k"]

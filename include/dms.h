@@ -37,7 +37,7 @@ typedef int32_t dms_status;
 /* Per-set status codes written to out_status arrays. */
 #define DMS_SET_OK 0      /* sketch computed */
 #define DMS_SET_EMPTY 1   /* no positive weight: the minhash is undefined (J = 0/0) */
-#define DMS_SET_RANGE 2   /* largest weight outside [2^-256, 2^256], or phi beyond its cap */
+#define DMS_SET_RANGE 2   /* largest weight outside [2^-768, 2^768], or phi beyond its cap */
 #define DMS_SET_INVALID 3 /* a negative, NaN or infinite weight */
 
 /* Engines for the sketch and LSH calls (dms_set_option DMS_OPT_ENGINE). */
@@ -235,7 +235,7 @@ const char* dms_status_str(dms_status s);
  * dms_t_of_k: t = ceil(k ln k) + k (proof of Theorem 1).
  * dms_spec_constants: for `seed` and t, the six hash keys (K_R, K_A, K_U, K_V,
  * K_S, K_L), the 20 Poisson(1) thresholds floor(2^64 P[Poi(1) <= n]), the
- * region corner tables W[300] = RN(RN(2^nu-1)/t) and R[300] = RN(2^rho-1), and
+ * region corners W[1024] = RN(RN(2^nu-1)/t) and R[1024] = RN(2^rho-1), and
  * u = RN(1/t).  Any output pointer may be NULL.  Errors: DMS_EINVAL (t = 0),
  * DMS_ESPEC.
  */

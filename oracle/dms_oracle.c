@@ -26,7 +26,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define DMSO_TABLE 300
+#define DMSO_TABLE 1024
 #define DMSO_NPOIS 20
 
 enum { DMSO_OK = 0, DMSO_EMPTY = 1, DMSO_RANGE = 2, DMSO_INVALID = 3, DMSO_NOMEM = 4 };
@@ -179,7 +179,7 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
 
 /* Validate a row: DMSO_INVALID for a negative, NaN or infinite weight,
  * DMSO_EMPTY when no weight is positive, DMSO_RANGE when the largest weight is
- * outside [2^-256, 2^256].  On success *S is the sum of the positive weights in
+ * outside [2^-768, 2^768].  On success *S is the sum of the positive weights in
  * row order. */
 static int check_row(int64_t nnz, const double* x, double* S)
 {
@@ -195,7 +195,7 @@ static int check_row(int64_t nnz, const double* x, double* S)
         }
     }
     if (!any) return DMSO_EMPTY;
-    if (mx > ldexp(1.0, 256) || mx < ldexp(1.0, -256)) return DMSO_RANGE;
+    if (mx > ldexp(1.0, 768) || mx < ldexp(1.0, -768)) return DMSO_RANGE;
     *S = sum;
     return DMSO_OK;
 }

@@ -31,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dms_oracle.c")
 LIB = os.path.join(HERE, "libdms_oracle.so")
 
-TABLE = 300
+TABLE = 1024
 NPOIS = 20
 STATUS = {"ok": 0, "empty": 1, "range": 2, "invalid": 3}
 SCHED_PLUS_ONE = 0   # phi = 1, 2, 3, ... (proof of Theorem 1)

@@ -461,8 +461,10 @@ dms_status dms_spec_constants(uint64_t seed, uint32_t t, uint64_t keys[6], uint6
         keys[3] = sp.key_v; keys[4] = sp.key_s; keys[5] = sp.key_l;
     }
     if (pois) std::memcpy(pois, sp.pois, sizeof sp.pois);
-    if (W) std::memcpy(W, sp.W, sizeof sp.W);
-    if (R) std::memcpy(R, sp.R, sizeof sp.R);
+    for (int i = 0; i < dms::kMaxIndex; ++i) {
+        if (W) W[i] = dms::corner_w(sp, i);
+        if (R) R[i] = dms::corner_r(sp, i);
+    }
     if (u) *u = sp.u;
     return DMS_OK;
 }

@@ -141,6 +141,9 @@ bool poisson_thresholds(uint64_t out[kNumPoisson])
     return true;
 }
 
+double corner_w(const SpecTables& sp, int nu) { return nu < kTable ? sp.W[nu] : std::ldexp(sp.u, nu); }
+double corner_r(const SpecTables& sp, int rho) { return rho < kTable ? sp.R[rho] : std::ldexp(1.0, rho); }
+
 void hash_keys(uint64_t seed, uint64_t keys[6])
 {
     std::mt19937_64 gen(seed);

@@ -33,6 +33,17 @@ __device__ __forceinline__ uint32_t poisson_count(const uint64_t* __restrict__ p
     return x;
 }
 
+// Lower corners of weight region nu and rank region rho: tables below kTable,
+// exact closed forms above (see corner_w / corner_r in dms_internal.h).
+__device__ __forceinline__ double w_corner(const double* tab, double u, int nu)
+{
+    return nu < kTable ? tab[nu] : ldexp(u, nu);
+}
+__device__ __forceinline__ double r_corner(const double* tab, int rho)
+{
+    return rho < kTable ? tab[rho] : ldexp(1.0, rho);
+}
+
 // bucket = (hi32(s) * n) >> 32
 __device__ __forceinline__ uint32_t bucket_of(uint64_t s, uint32_t n)
 {
@@ -106,7 +117,7 @@ __device__ __forceinline__ RowInfo scan_row(const double* __restrict__ w, int64_
     mx = wave_max(mx);
     if (wave_any(bad)) ri.status = kSetInvalid;
     else if (!(mx > 0.0)) ri.status = kSetEmpty;
-    else if (mx > 0x1.0p256 || mx < 0x1.0p-256) ri.status = kSetRange;
+    else if (mx > 0x1.0p768 || mx < 0x1.0p-768) ri.status = kSetRange;
     else ri.status = kSetOk;
     return ri;
 }

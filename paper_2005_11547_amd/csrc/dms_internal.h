@@ -6,14 +6,15 @@
 
 namespace dms {
 
-constexpr int kTable = 300;     // region corner tables, nu and rho < 300
+constexpr int kTable = 64;      // region corners kept in tables (nu, rho < 64)
+constexpr int kMaxIndex = 1024; // nu and rho stay below this in the supported domain
 constexpr int kNumPoisson = 20; // Poisson(1) thresholds for n = 0..19
 
 // Everything a kernel needs to generate darts for one value of t.  Lives in
 // device memory, one copy per t, owned by the context.
 struct SpecTables {
-    double W[kTable];       // W[nu]  = RN(RN(2^nu - 1) / t)
-    double R[kTable];       // R[rho] = RN(2^rho - 1)
+    double W[kTable];       // W[nu]  = RN(RN(2^nu - 1) / t); for nu >= 54 it equals ldexp(u, nu)
+    double R[kTable];       // R[rho] = RN(2^rho - 1);        for rho >= 54 it equals 2^rho
     uint64_t pois[kNumPoisson];
     uint64_t key_r, key_a, key_u, key_v, key_s, key_l;
     double u;               // RN(1/t)
@@ -25,6 +26,12 @@ uint32_t t_of_k(int32_t k);
 bool poisson_thresholds(uint64_t out[kNumPoisson]);
 void hash_keys(uint64_t seed, uint64_t keys[6]);
 bool make_spec(uint64_t seed, uint32_t t, SpecTables* sp);
+
+// Region corners for any index.  For nu >= 54, RN(2^nu - 1) = 2^nu and
+// RN(2^nu / t) = 2^nu * RN(1/t) (scaling by a power of two is exact), so the
+// corners past the tables are exact powers of two times u, resp. 1.
+double corner_w(const SpecTables& sp, int nu);
+double corner_r(const SpecTables& sp, int rho);
 
 // Per-set status values written to out_status.
 enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3 };

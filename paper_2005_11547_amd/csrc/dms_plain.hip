@@ -21,12 +21,12 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
         const double xi = w[e];
         if (!(xi > 0.0)) continue;
         const uint64_t id = (uint32_t)idx[e];
-        for (int nu = 0; sp->W[nu] <= xi; ++nu) {
-            if (nu + 1 >= kTable) { *range = true; break; }
-            const double Wn = sp->W[nu];
-            for (int rho = 0; sp->R[rho] <= tau; ++rho) {
-                if (rho + 1 >= kTable) { *range = true; break; }
-                const double Rr = sp->R[rho];
+        for (int nu = 0; w_corner(sp->W, sp->u, nu) <= xi; ++nu) {
+            if (nu + 1 >= kMaxIndex) { *range = true; break; }
+            const double Wn = w_corner(sp->W, sp->u, nu);
+            for (int rho = 0; r_corner(sp->R, rho) <= tau; ++rho) {
+                if (rho + 1 >= kMaxIndex) { *range = true; break; }
+                const double Rr = r_corner(sp->R, rho);
                 const double dnu = ldexp(sp->u, nu - rho);
                 const double drho = ldexp(1.0, rho - nu);
                 const uint64_t g =

@@ -96,12 +96,12 @@ constexpr uint32_t kOffPqRank = kOffPqX + 8 * kCapP;         // u64[kCapP] rank 
 constexpr uint32_t kOffRqRc = kOffPqRank + 8 * kCapP;        // u32[kCapR] rows
 constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCapR;          // u32[kCapR] areas
 constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCapR;       // u32[kCapR] areas taken
-constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | rho << 9
+constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | rho << 10
 constexpr uint32_t kOffDqR = kOffRqM + 4 * kCapR;            // u32[kCapD]
 constexpr uint32_t kOffDqW = kOffDqR + 4 * kCapD;            // u32[kCapD]
-constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<9|j<<18|X<<23
+constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<10|j<<20|X<<25
 constexpr uint32_t kOffPqW = kOffDqM + 4 * kCapD;            // u32[kCapP]
-constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<9|j<<18
+constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<10|j<<20
 constexpr uint32_t kOffMark = kOffPqM + 4 * kCapP;           // i32[64]
 constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits, u64[k] ids
 constexpr uint32_t kQueueBytes = kOffBins;
@@ -264,8 +264,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 const double tau = phi / S;
                 // rho runs over 0 .. B1-1: the rows whose lower corner is <= tau
                 int B1 = 0;
-                while (B1 < kTable && sR[B1] <= tau) ++B1;
-                bool range = B1 >= kTable;
+                while (B1 < kMaxIndex && r_corner(sR, B1) <= tau) ++B1;
+                bool range = B1 >= kMaxIndex;
                 const float inv_b1 = 1.0f / (float)B1;
 
                 const int64_t b1 = hi;
@@ -294,10 +294,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         if (ex > 0.0) {
                             // weight rows: nu with W[nu] <= x (W[0] = 0)
                             int A = ilogb(1.0 + td * ex) + 1;
-                            A = A < 1 ? 1 : (A > kTable ? kTable : A);
-                            while (A < kTable && sW[A] <= ex) ++A;
-                            while (A > 1 && sW[A - 1] > ex) --A;
-                            if (A >= kTable) range = true;
+                            A = A < 1 ? 1 : (A > kMaxIndex ? kMaxIndex : A);
+                            while (A < kMaxIndex && w_corner(sW, u, A) <= ex) ++A;
+                            while (A > 1 && w_corner(sW, u, A - 1) > ex) --A;
+                            if (A >= kMaxIndex) range = true;
                             nreg = (uint32_t)A * (uint32_t)B1;
                         }
                         const uint32_t incl = scan_add(nreg);
@@ -322,10 +322,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t wv = at<uint32_t>(wb, kOffPqW, pos);
                         const uint32_t meta = at<uint32_t>(wb, kOffPqM, pos);
                         const uint64_t rb = at<uint64_t>(wb, kOffPqRank, pos);
-                        const int nu = meta & 511, rho = (meta >> 9) & 511;
-                        const uint64_t j = (meta >> 18) & 31;
+                        const int nu = meta & 1023, rho = (meta >> 10) & 1023;
+                        const uint64_t j = (meta >> 20) & 31;
                         const double V = unit53(mix64(a ^ KV ^ j));
-                        const double weight = sW[nu] + ((double)wv + V) * ldexp(u, nu - rho);
+                        const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         uint64_t s = 0;
                         if (acc) s = mix64(a ^ KS ^ j);
@@ -346,10 +346,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t rv = at<uint32_t>(wb, kOffDqR, rpos);
                         const uint32_t wv = at<uint32_t>(wb, kOffDqW, rpos);
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
-                        const int nu = meta & 511, rho = (meta >> 9) & 511;
-                        const uint32_t j = (meta >> 18) & 31, X = meta >> 23;
+                        const int nu = meta & 1023, rho = (meta >> 10) & 1023;
+                        const uint32_t j = (meta >> 20) & 31, X = meta >> 25;
                         const double U = unit53(mix64(a ^ KU ^ (uint64_t)j));
-                        const double rank = sR[rho] + ((double)rv + U) * ldexp(1.0, rho - nu);
+                        const double rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                         const bool pass = act && rank <= tau && rank > tau_prev;
                         const bool more = act && j + 1 < X;
                         const uint64_t bp = __ballot(pass);
@@ -361,7 +361,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<double>(wb, kOffPqX, pos) = xi;
                             at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
                             at<uint32_t>(wb, kOffPqW, pos) = wv;
-                            at<uint32_t>(wb, kOffPqM, pos) = meta & ((1u << 23) - 1);
+                            at<uint32_t>(wb, kOffPqM, pos) = meta & ((1u << 25) - 1);
                         }
                         const uint32_t dq_left = dq_count - m;
                         if (more) {
@@ -370,7 +370,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<double>(wb, kOffDqX, pos) = xi;
                             at<uint32_t>(wb, kOffDqR, pos) = rv;
                             at<uint32_t>(wb, kOffDqW, pos) = wv;
-                            at<uint32_t>(wb, kOffDqM, pos) = meta + (1u << 18);
+                            at<uint32_t>(wb, kOffDqM, pos) = meta + (1u << 20);
                         }
                         pq_count = uni(pq_count + (uint32_t)__popcll(bp));
                         dq_head = uni((dq_head + m) & (kCapD - 1));
@@ -432,7 +432,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<double>(wb, kOffDqX, pos) = xi;
                             at<uint32_t>(wb, kOffDqR, pos) = rv;
                             at<uint32_t>(wb, kOffDqW, pos) = wv;
-                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 23);
+                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25);
                         }
                         dq_count = uni(dq_count + (uint32_t)__popcll(bpush));
                         // advance the region queue by m areas
@@ -473,7 +473,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 while ((nu + 1) * (uint32_t)B1 <= local) ++nu;
                                 rho = local - nu * (uint32_t)B1;
                             }
-                            meta = nu | (rho << 9);
+                            meta = nu | (rho << 10);
                             g = mix64(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16) | rho));
                             double wc = 1.0, rcn;
                             if (rho == 0) {
@@ -482,7 +482,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rcn = floor(ldexp(tau, (int)nu)) + 1.0;
                                 rcn = rcn < rcap ? rcn : rcap;
                             } else {
-                                const double Wn = sW[nu], Rr = sR[rho];
+                                const double Wn = w_corner(sW, u, (int)nu), Rr = r_corner(sR, (int)rho);
                                 const double dnu = ldexp(u, (int)nu - (int)rho);
                                 const double drho = ldexp(1.0, (int)rho - (int)nu);
                                 const double wcap = ldexp(1.0, (int)rho);
@@ -514,7 +514,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<double>(wb, kOffDqX, pos) = x;
                             at<uint32_t>(wb, kOffDqR, pos) = 0;
                             at<uint32_t>(wb, kOffDqW, pos) = 0;
-                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 23);
+                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25);
                         }
                         if (push_r) {
                             const uint32_t pos = (rq_head + rq_count + rank_in(br)) & (kCapR - 1);

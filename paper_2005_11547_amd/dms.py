@@ -99,8 +99,8 @@ def spec_constants(seed: int, t: int) -> dict:
     import numpy as np
     keys = np.zeros(6, np.uint64)
     pois = np.zeros(20, np.uint64)
-    W = np.zeros(300, np.float64)
-    R = np.zeros(300, np.float64)
+    W = np.zeros(1024, np.float64)
+    R = np.zeros(1024, np.float64)
     u = ctypes.c_double(0.0)
     st = lib().dms_spec_constants(seed, t, _ptr(keys), _ptr(pois), _ptr(W), _ptr(R), ctypes.byref(u))
     if st != DMS_OK:

@@ -73,10 +73,12 @@ def test_edge_rows(torch, ctx):
         ([1, 2, 3], [0.5, -1.0, 2.0]),              # negative weight
         ([1, 2], [np.nan, 1.0]),                    # NaN
         ([1, 2], [np.inf, 1.0]),                    # infinity
-        ([7], [2.0 ** 300]),                        # beyond the supported range
-        ([7], [2.0 ** -300]),                       # below it
-        ([7], [2.0 ** 250]),                        # huge but inside
-        ([7], [2.0 ** -250]),                       # tiny but inside
+        ([7], [2.0 ** 800]),                        # beyond the supported range
+        ([7], [2.0 ** -800]),                       # below it
+        ([7], [2.0 ** 700]),                        # huge but inside
+        ([7], [2.0 ** -700]),                       # tiny but inside
+        ([7, 8], [2.0 ** 512, 3.0]),                # the paper's largest ||x||_1
+        ([7, 8], [2.0 ** -513, 2.0 ** -513]),       # and its smallest
         ([123], [1.0]),                             # single element
         ([1, 2, 3], [1e-300, 1.0, 0.0]),            # denormal-scale element
         ([4, 4, 9], [0.3, 0.7, 1.0]),               # repeated id (acts as the max weight)
@@ -163,7 +165,7 @@ def test_heavy_sets_cut_into_parts(torch, split):
     # by the last one; the result may not depend on the cut.
     from paper_2005_11547_amd import Context, dms
     rp, idx, w = WL.batch_k256(seed=21, n_sets=30)
-    extra = [([5, 9], [0.0, 0.0]), ([1, 2, 3], [0.5, -1.0, 2.0]), ([7], [2.0 ** 300]),
+    extra = [([5, 9], [0.0, 0.0]), ([1, 2, 3], [0.5, -1.0, 2.0]), ([7], [2.0 ** 800]),
              ([4, 4, 9, 9, 11], [0.3, 0.7, 1.0, 0.2, 0.5]),
              (list(range(1000)), [0.0] * 500 + [1.0] * 500)]
     rows = [(idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]) for r in range(len(rp) - 1)] + extra

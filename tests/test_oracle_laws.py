@@ -156,8 +156,12 @@ def test_special_cases():
     assert O.minhash_set(ids, bad, 8, SEED)[0] == O.STATUS["invalid"]
     bad[3] = np.inf
     assert O.minhash_set(ids, bad, 8, SEED)[0] == O.STATUS["invalid"]
-    big = w.copy(); big[0] = 2.0 ** 300
+    big = w.copy(); big[0] = 2.0 ** 800
     assert O.minhash_set(ids, big, 8, SEED)[0] == O.STATUS["range"]
+    big[0] = 2.0 ** 700          # extreme but inside the supported domain
+    assert O.minhash_set(ids, big, 8, SEED)[0] == O.STATUS["ok"]
+    tiny = np.array([2.0 ** -800])
+    assert O.minhash_set(ids[:1], tiny, 8, SEED)[0] == O.STATUS["range"]
     # zero weights are skipped: same sketch as without the element
     z = w.copy(); z[7] = 0.0
     keep = np.arange(len(ids)) != 7
