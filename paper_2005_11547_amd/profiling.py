@@ -57,9 +57,10 @@ def write_trace(db_path: str, out: str, command: str):
     with open(out, "w") as f:
         f.write("# rocprofv3 kernel trace summary\n\n")
         f.write(f"Command (from the repository root):\n\n    {command}\n\n")
-        f.write("| kernel | calls | total us | average us | % |\n|---|---|---|---|---|\n")
+        # the top_kernels view reports microseconds
+        f.write("| kernel | calls | total ms | average ms | % |\n|---|---|---|---|---|\n")
         for n, c, t, a, p in rows:
-            f.write(f"| {_short(n)} | {c} | {t / 1e3:.1f} | {a / 1e3:.3f} | {p:.2f} |\n")
+            f.write(f"| {_short(n)} | {c} | {t / 1e3:.3f} | {a / 1e3:.3f} | {p:.2f} |\n")
         f.write(f"\nKernel sources hash: {source_hash()}\n")
 
 
