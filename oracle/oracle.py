@@ -10,7 +10,8 @@ Layout:
   with exact arithmetic (``fractions``/``decimal``) and IEEE binary64 division;
 * a ctypes wrapper around ``dms_oracle.c`` (the single-threaded DartHash,
   DartMinHash and LSH loops);
-* the two estimators and the Hamming top-k scan, written directly with numpy.
+* the estimators, the b-bit fingerprints and their packing, the unary
+  feature map and the Hamming top-k scan, written directly with numpy.
 
 Paper references are to Christiani, "DartMinHash: Fast Sketching for Weighted
 Sets" (arXiv 2005.11547).
@@ -23,6 +24,7 @@ import subprocess
 from decimal import Decimal, getcontext
 from fractions import Fraction
 from functools import lru_cache
+import math
 from math import factorial
 
 import numpy as np
@@ -362,3 +364,62 @@ def hamming_topk(db_bits, q_bits, topk: int):
         ids[qi, :len(order)] = order
         dist[qi, :len(order)] = d[order]
     return ids, dist
+
+
+# --------------------------------------------------------------------------
+# b-bit fingerprints and the unary feature map (Section 1.1)
+# --------------------------------------------------------------------------
+def bbit_values(minhash_u32, b: int):
+    """The b-bit fingerprint of each minhash: its lowest b bits (bits of the
+    dart-id hash s, independent of the bucket bits; b = 1 is the 1-bit sketch)."""
+    v = np.asarray(minhash_u32, dtype=np.uint64)
+    return v & np.uint64((1 << b) - 1)
+
+
+def bbit_words(k: int, b: int) -> int:
+    return (k * b + 63) // 64
+
+
+def bbit_pack(minhash_u32, b: int):
+    """Pack the k fingerprints of each row into ceil(k*b/64) little-endian
+    uint64 words: fingerprint j occupies stream bits [j*b, j*b + b), stream
+    bit p is bit p % 64 of word p // 64, unused high bits are zero."""
+    v = bbit_values(minhash_u32, b)
+    n, k = v.shape
+    words = bbit_words(k, b)
+    stream = np.zeros((n, words * 64), dtype=np.uint8)
+    for i in range(b):  # bit i of every fingerprint
+        stream[:, np.arange(k) * b + i] = ((v >> np.uint64(i)) & np.uint64(1)).astype(np.uint8)
+    packed = np.packbits(stream, axis=1, bitorder="little")  # byte q holds stream bits 8q..8q+7
+    return packed.view("<u8").reshape(n, words).astype(np.uint64)
+
+
+def bbit_unpack(words, k: int, b: int):
+    """Inverse of bbit_pack: the k fingerprints of each row."""
+    w = np.ascontiguousarray(np.asarray(words, dtype="<u8"))
+    n = w.shape[0]
+    stream = np.unpackbits(w.view(np.uint8).reshape(n, -1), axis=1, bitorder="little")
+    out = np.zeros((n, k), dtype=np.uint64)
+    for i in range(b):
+        out |= stream[:, np.arange(k) * b + i].astype(np.uint64) << np.uint64(i)
+    return out
+
+
+def jaccard_est_bbit(a_words, b_words, k: int, b: int):
+    """b-bit sketches: fingerprints of one bucket agree with probability
+    J + (1 - J) 2^-b, so J-hat = (m/k - 2^-b) / (1 - 2^-b) with m the number of
+    agreeing fingerprints (unclamped)."""
+    m = (bbit_unpack(a_words, k, b) == bbit_unpack(b_words, k, b)).sum(axis=-1)
+    c = 2.0 ** -b
+    return (m / k - c) / (1.0 - c)
+
+
+def unary_map(minhash_u32, b: int):
+    """Linearisation of the Jaccard kernel: minhash j with fingerprint v maps to
+    the unit vector of coordinate j*2^b + v, and the row is scaled by 1/sqrt(k),
+    so <u(x), u(y)> = (agreeing fingerprints)/k.  Returns (indices [n, k] int32,
+    ascending within a row, and the common value 1/sqrt(k))."""
+    v = bbit_values(minhash_u32, b).astype(np.int64)
+    n, k = v.shape
+    idx = (np.arange(k, dtype=np.int64) << b)[None, :] + v
+    return idx.astype(np.int32), 1.0 / math.sqrt(k)
