@@ -137,6 +137,48 @@ dms_status dms_jaccard_est(dms_ctx ctx, int64_t n_pairs, const void* a, const vo
                            int32_t format, double* out);
 
 /*
+ * b-bit fingerprints (Section 1.1, similarity estimation): the fingerprint of
+ * a minhash is its lowest `bits` bits (bits of the dart-id hash, independent of
+ * the bucket bits; bits = 1 gives the 1-bit sketch of dms_sketch_csr).  Row s's
+ * k fingerprints are packed into words = ceil(k*bits/64) uint64 words:
+ * fingerprint j occupies stream bits [j*bits, j*bits + bits), stream bit p is
+ * bit p%64 of word p/64, and the unused high bits of the last word are zero.
+ *   minhash device uint32[n_sets*k]     (out_u32 of dms_sketch_csr)
+ *   out     device uint64[n_sets*words]
+ *   k 1..2^20, bits 1..32
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_bbit_pack(dms_ctx ctx, int64_t n_sets, const uint32_t* minhash, int32_t k,
+                         int32_t bits, uint64_t* out);
+
+/*
+ * Weighted Jaccard estimate from two packed b-bit sketches (layout of
+ * dms_bbit_pack).  Fingerprints of one bucket agree with probability
+ * J + (1 - J) 2^-bits, so out[p] = (m/k - 2^-bits) / (1 - 2^-bits) with m the
+ * number of agreeing fingerprints of pair p (not clamped).  Bits past k*bits
+ * in the last word are ignored.
+ *   a, b device uint64[n_pairs*words]; out device float64[n_pairs]
+ *   k 1..2^20, bits 1..32
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_jaccard_est_bbit(dms_ctx ctx, int64_t n_pairs, const uint64_t* a, const uint64_t* b,
+                                int32_t k, int32_t bits, double* out);
+
+/*
+ * Unary feature map of b-bit minhashes (Section 1.1, large-scale kernel
+ * machines): row s becomes the k*2^bits dimensional vector with value
+ * 1/sqrt(k) at the k coordinates j*2^bits + fingerprint_j and zero elsewhere,
+ * so the inner product of two rows is the fraction of agreeing fingerprints.
+ *   minhash   device uint32[n_sets*k]
+ *   out_index device int32[n_sets*k]   (ascending within a row)
+ *   out_scale host double* or NULL     (receives 1/sqrt(k))
+ *   k >= 1, bits 1..16, k*2^bits <= 2^31
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_unary_map(dms_ctx ctx, int64_t n_sets, const uint32_t* minhash, int32_t k,
+                         int32_t bits, int32_t* out_index, double* out_scale);
+
+/*
  * Hamming top-k search over 1-bit sketches (the similarity-search use of
  * Section 1.1): for every query row q, the `topk` database rows with the
  * smallest Hamming distance, ascending by (distance, row id).

@@ -53,6 +53,12 @@ hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uin
                           uint64_t* partial, int n_blocks, hipStream_t st);
 hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks,
                      hipStream_t st);
+hipError_t launch_bbit_pack(int64_t n_sets, const uint32_t* v, int k, int b, uint64_t* out,
+                            hipStream_t st);
+hipError_t launch_bbit_jaccard(int64_t n_pairs, const uint64_t* a, const uint64_t* b_, int k, int b,
+                               double* out, hipStream_t st);
+hipError_t launch_unary_map(int64_t n_sets, const uint32_t* v, int k, int b, int32_t* out,
+                            hipStream_t st);
 hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
                           double* out, hipStream_t st);
 }  // namespace dms
@@ -361,6 +367,52 @@ dms_status dms_jaccard_est(dms_ctx c, int64_t n_pairs, const void* a, const void
     DeviceGuard g(c->device);
     hipError_t e = dms::launch_jaccard(n_pairs, a, b, k, format, out, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "jaccard launch");
+    return DMS_OK;
+}
+
+dms_status dms_bbit_pack(dms_ctx c, int64_t n_sets, const uint32_t* minhash, int32_t k, int32_t bits,
+                         uint64_t* out)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 0 || k < 1 || k > (1 << 20) || bits < 1 || bits > 32)
+        return fail(c, DMS_EINVAL, "bad n_sets, k or bits");
+    if (n_sets == 0) return DMS_OK;
+    if (!minhash || !out) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipError_t e = dms::launch_bbit_pack(n_sets, minhash, k, bits, out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "b-bit pack launch");
+    return DMS_OK;
+}
+
+dms_status dms_jaccard_est_bbit(dms_ctx c, int64_t n_pairs, const uint64_t* a, const uint64_t* b,
+                                int32_t k, int32_t bits, double* out)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_pairs < 0 || k < 1 || k > (1 << 20) || bits < 1 || bits > 32)
+        return fail(c, DMS_EINVAL, "bad n_pairs, k or bits");
+    if (n_pairs == 0) return DMS_OK;
+    if (!a || !b || !out) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipError_t e = dms::launch_bbit_jaccard(n_pairs, a, b, k, bits, out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "b-bit jaccard launch");
+    return DMS_OK;
+}
+
+dms_status dms_unary_map(dms_ctx c, int64_t n_sets, const uint32_t* minhash, int32_t k, int32_t bits,
+                         int32_t* out_index, double* out_scale)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 0 || k < 1 || bits < 1 || bits > 16 || ((int64_t)k << bits) > (int64_t(1) << 31))
+        return fail(c, DMS_EINVAL, "bad n_sets, k or bits");
+    if (out_scale) *out_scale = 1.0 / std::sqrt((double)k);
+    if (n_sets == 0) return DMS_OK;
+    if (!minhash || !out_index) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipError_t e = dms::launch_unary_map(n_sets, minhash, k, bits, out_index, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "unary map launch");
     return DMS_OK;
 }
 

@@ -21,7 +21,8 @@ FMT_U32, FMT_1BIT = 0, 1
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
-           "dms_server_create", "dms_server_destroy", "dms_server_replay"]
+           "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
+           "dms_jaccard_est_bbit", "dms_unary_map"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -58,6 +59,9 @@ def lib():
         "dms_sketch_csr": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
         "dms_lsh_keys": ([vp, i64, vp, vp, vp, i32, i32, vp, vp], i32),
         "dms_jaccard_est": ([vp, i64, vp, vp, i32, i32, vp], i32),
+        "dms_bbit_pack": ([vp, i64, vp, i32, i32, vp], i32),
+        "dms_jaccard_est_bbit": ([vp, i64, vp, vp, i32, i32, vp], i32),
+        "dms_unary_map": ([vp, i64, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "dms_hamming_topk": ([vp, vp, i64, i32, vp, i64, i32, vp, vp], i32),
         "dms_sync": ([vp], i32),
         "dms_last_error": ([vp], ctypes.c_char_p),
@@ -167,6 +171,22 @@ class Context:
         self._check(lib().dms_jaccard_est(self._h, n_pairs, _ptr(a), _ptr(b), k, fmt, _ptr(out)),
                     "dms_jaccard_est")
 
+    def dms_bbit_pack(self, n_sets, minhash, k, bits, out):
+        self._stream()
+        self._check(lib().dms_bbit_pack(self._h, n_sets, _ptr(minhash), k, bits, _ptr(out)), "dms_bbit_pack")
+
+    def dms_jaccard_est_bbit(self, n_pairs, a, b, k, bits, out):
+        self._stream()
+        self._check(lib().dms_jaccard_est_bbit(self._h, n_pairs, _ptr(a), _ptr(b), k, bits, _ptr(out)),
+                    "dms_jaccard_est_bbit")
+
+    def dms_unary_map(self, n_sets, minhash, k, bits, out_index):
+        self._stream()
+        scale = ctypes.c_double(0.0)
+        self._check(lib().dms_unary_map(self._h, n_sets, _ptr(minhash), k, bits, _ptr(out_index),
+                                        ctypes.byref(scale)), "dms_unary_map")
+        return scale.value
+
     def dms_hamming_topk(self, db, n_db, words, queries, n_q, topk, out_ids, out_dist):
         self._stream()
         self._check(lib().dms_hamming_topk(self._h, _ptr(db), n_db, words, _ptr(queries), n_q, topk,
@@ -214,6 +234,29 @@ class Context:
         out = torch.empty(a.shape[0], dtype=torch.float64, device=a.device)
         self.dms_jaccard_est(a.shape[0], a, b, k, fmt, out)
         return out
+
+    def bbit_pack(self, minhash, bits):
+        """Packed b-bit fingerprints of [n, k] uint32 minhashes (stored as int32):
+        int64 [n, ceil(k*bits/64)]."""
+        torch = self._torch
+        n, k = minhash.shape
+        out = torch.empty((n, (k * bits + 63) // 64), dtype=torch.int64, device=minhash.device)
+        self.dms_bbit_pack(n, minhash, k, bits, out)
+        return out
+
+    def jaccard_bbit(self, a, b, k, bits):
+        torch = self._torch
+        out = torch.empty(a.shape[0], dtype=torch.float64, device=a.device)
+        self.dms_jaccard_est_bbit(a.shape[0], a, b, k, bits, out)
+        return out
+
+    def unary_map(self, minhash, bits):
+        """(int32 [n, k] coordinates, common value 1/sqrt(k))."""
+        torch = self._torch
+        n, k = minhash.shape
+        out = torch.empty((n, k), dtype=torch.int32, device=minhash.device)
+        scale = self.dms_unary_map(n, minhash, k, bits, out)
+        return out, scale
 
     def hamming_topk(self, db, queries, topk):
         torch = self._torch
