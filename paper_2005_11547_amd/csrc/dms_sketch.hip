@@ -7,13 +7,14 @@
 //
 //   region round : expands elements into their (nu, rho) regions, hashes the
 //                  region (g) and its first area (a), draws that area's
-//                  Poisson(1) dart count; regions with more areas go to the
-//                  region queue, areas with darts to the dart queue.
+//                  Poisson(1) dart count and its first dart's rank; regions
+//                  with more areas go to the region queue, passing darts to
+//                  the pass queue, areas with more darts to the dart queue.
 //   area round   : expands queued regions into their remaining areas, hashes
-//                  them and draws their dart counts.
-//   dart round   : draws the rank uniform of one dart per queued area; darts
-//                  with rank <= tau go to the pass queue; an area with more
-//                  darts goes back to the dart queue.
+//                  them, draws their dart counts and first ranks (as above).
+//   dart round   : draws the rank uniform of the next dart of each queued
+//                  area; darts with rank <= tau go to the pass queue; an area
+//                  with more darts goes back to the dart queue.
 //   accept round : draws the weight uniform; darts with weight <= x_i get their
 //                  id hash and enter the bucket minima.
 //
@@ -310,6 +311,45 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 };
                 load_chunk();
 
+                // An area that holds X > 0 darts: the rank uniform of its first dart
+                // is drawn at once; a dart inside (tau_prev, tau] enters the pass
+                // queue, and an area with more darts enters the dart queue at j = 1.
+                // Called by all 64 lanes; the `act` lanes carry an area.  Region
+                // and area rounds run only while both queues hold fewer than 64
+                // entries, so neither can overflow.
+                auto emit_area = [&](bool act, uint64_t a, double xi, uint32_t rv, uint32_t wv,
+                                     uint32_t meta, uint32_t X) {
+                    const bool has = act && X > 0;
+                    double rank = 0.0;
+                    if (has) {
+                        const int nu = meta & 1023, rho = (meta >> 10) & 1023;
+                        const double U = unit53(mix64(a ^ KU));
+                        rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
+                    }
+                    const bool pass = has && rank <= tau && rank > tau_prev;
+                    const bool more = has && X > 1;
+                    const uint64_t bp = __ballot(pass);
+                    const uint64_t bm = __ballot(more);
+                    if (pass) {
+                        const uint32_t pos = (pq_head + pq_count + rank_in(bp)) & (kCapP - 1);
+                        at<uint64_t>(wb, kOffPqA, pos) = a;
+                        at<double>(wb, kOffPqX, pos) = xi;
+                        at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
+                        at<uint32_t>(wb, kOffPqW, pos) = wv;
+                        at<uint32_t>(wb, kOffPqM, pos) = meta;
+                    }
+                    if (more) {
+                        const uint32_t pos = (dq_head + dq_count + rank_in(bm)) & (kCapD - 1);
+                        at<uint64_t>(wb, kOffDqA, pos) = a;
+                        at<double>(wb, kOffDqX, pos) = xi;
+                        at<uint32_t>(wb, kOffDqR, pos) = rv;
+                        at<uint32_t>(wb, kOffDqW, pos) = wv;
+                        at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25) | (1u << 20);
+                    }
+                    pq_count = uni(pq_count + (uint32_t)__popcll(bp));
+                    dq_count = uni(dq_count + (uint32_t)__popcll(bm));
+                };
+
                 for (;;) {
                     wave_sync();
                     if (pq_count >= 64 || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
@@ -424,17 +464,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             a = mix64(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = poisson_fast(C, sPois, a);
                         }
-                        const bool push = act && X > 0;
-                        const uint64_t bpush = __ballot(push);
-                        if (push) {
-                            const uint32_t pos = (dq_head + dq_count + rank_in(bpush)) & (kCapD - 1);
-                            at<uint64_t>(wb, kOffDqA, pos) = a;
-                            at<double>(wb, kOffDqX, pos) = xi;
-                            at<uint32_t>(wb, kOffDqR, pos) = rv;
-                            at<uint32_t>(wb, kOffDqW, pos) = wv;
-                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25);
-                        }
-                        dq_count = uni(dq_count + (uint32_t)__popcll(bpush));
+                        emit_area(act, a, xi, rv, wv, meta, X);
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
                         const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
@@ -504,18 +534,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             X = poisson_fast(C, sPois, a);
                             rest = nau - 1;
                         }
-                        const bool push_d = act && X > 0;
+                        emit_area(act, a, x, 0u, 0u, meta, X);
                         const bool push_r = act && rest > 0;
-                        const uint64_t bd = __ballot(push_d);
                         const uint64_t br = __ballot(push_r);
-                        if (push_d) {
-                            const uint32_t pos = (dq_head + dq_count + rank_in(bd)) & (kCapD - 1);
-                            at<uint64_t>(wb, kOffDqA, pos) = a;
-                            at<double>(wb, kOffDqX, pos) = x;
-                            at<uint32_t>(wb, kOffDqR, pos) = 0;
-                            at<uint32_t>(wb, kOffDqW, pos) = 0;
-                            at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25);
-                        }
                         if (push_r) {
                             const uint32_t pos = (rq_head + rq_count + rank_in(br)) & (kCapR - 1);
                             at<uint64_t>(wb, kOffRqG, pos) = g;
@@ -525,7 +546,6 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<uint32_t>(wb, kOffRqFirst, pos) = 1;
                             at<uint32_t>(wb, kOffRqM, pos) = meta;
                         }
-                        dq_count = uni(dq_count + (uint32_t)__popcll(bd));
                         rq_count = uni(rq_count + (uint32_t)__popcll(br));
                         // areas added to the region queue, each region counted at most 64 times:
                         // a lower bound that only steers when area rounds run full
