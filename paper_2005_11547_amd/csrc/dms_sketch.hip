@@ -28,9 +28,19 @@ namespace dms {
 
 namespace {
 
-constexpr int kCapR = 128;  // region queue (regions with areas left)
-constexpr int kCapD = 128;  // dart queue (areas with darts left)
-constexpr int kCapP = 128;  // pass queue (darts with rank <= tau)
+// Every queue is a ring of kCap entries.  A round consumes up to 64 entries
+// and pushes at most 64 into each queue it feeds, and it runs only while every
+// queue it feeds holds at most kTrig entries (consumers take priority above
+// that), so kTrig + 64 <= kCap keeps the rings from overflowing.
+constexpr uint32_t kCap = 96;
+constexpr uint32_t kTrig = kCap - 64;
+
+// Ring slot of a position p < 3 * kCap (head < kCap plus two counts).
+__device__ __forceinline__ uint32_t ring(uint32_t p)
+{
+    p = min(p, p - 2u * kCap);  // unsigned: wraps to a large value when p < 2 * kCap
+    return min(p, p - kCap);
+}
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -87,23 +97,25 @@ __device__ __forceinline__ uint32_t poisson_fast(const uint64_t (&C)[8], const u
 // LDS of one wave: queues at fixed offsets from the wave's base, then the k
 // bucket minima.  Offsets are compile-time constants so that every access is
 // one base register plus an immediate.
-constexpr uint32_t kOffRqG = 0;                              // u64[kCapR] region hash
-constexpr uint32_t kOffRqX = kOffRqG + 8 * kCapR;            // f64[kCapR] element weight
-constexpr uint32_t kOffDqA = kOffRqX + 8 * kCapR;            // u64[kCapD] area hash
-constexpr uint32_t kOffDqX = kOffDqA + 8 * kCapD;            // f64[kCapD]
-constexpr uint32_t kOffPqA = kOffDqX + 8 * kCapD;            // u64[kCapP]
-constexpr uint32_t kOffPqX = kOffPqA + 8 * kCapP;            // f64[kCapP]
-constexpr uint32_t kOffPqRank = kOffPqX + 8 * kCapP;         // u64[kCapP] rank bits
-constexpr uint32_t kOffRqRc = kOffPqRank + 8 * kCapP;        // u32[kCapR] rows
-constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCapR;          // u32[kCapR] areas
-constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCapR;       // u32[kCapR] areas taken
-constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | rho << 10
-constexpr uint32_t kOffDqR = kOffRqM + 4 * kCapR;            // u32[kCapD]
-constexpr uint32_t kOffDqW = kOffDqR + 4 * kCapD;            // u32[kCapD]
-constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<10|j<<20|X<<25
-constexpr uint32_t kOffPqW = kOffDqM + 4 * kCapD;            // u32[kCapP]
-constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<10|j<<20
-constexpr uint32_t kOffMark = kOffPqM + 4 * kCapP;           // i32[64]
+// Entries name their element by its offset e from the first element of the
+// pass (the weight itself is read back from the CSR only by the accept round).
+constexpr uint32_t kOffRqG = 0;                              // u64[kCap] region hash
+constexpr uint32_t kOffDqA = kOffRqG + 8 * kCap;             // u64[kCap] area hash
+constexpr uint32_t kOffPqA = kOffDqA + 8 * kCap;             // u64[kCap] area hash
+constexpr uint32_t kOffPqRank = kOffPqA + 8 * kCap;          // u64[kCap] rank bits
+constexpr uint32_t kOffRqE = kOffPqRank + 8 * kCap;          // u32[kCap] element offset
+constexpr uint32_t kOffRqRc = kOffRqE + 4 * kCap;            // u32[kCap] rows
+constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCap;           // u32[kCap] areas
+constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCap;        // u32[kCap] areas taken
+constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCap;         // u32[kCap] nu | rho << 10
+constexpr uint32_t kOffDqE = kOffRqM + 4 * kCap;             // u32[kCap]
+constexpr uint32_t kOffDqR = kOffDqE + 4 * kCap;             // u32[kCap]
+constexpr uint32_t kOffDqW = kOffDqR + 4 * kCap;             // u32[kCap]
+constexpr uint32_t kOffDqM = kOffDqW + 4 * kCap;             // u32[kCap] nu|rho<<10|j<<20|X<<25
+constexpr uint32_t kOffPqE = kOffDqM + 4 * kCap;             // u32[kCap]
+constexpr uint32_t kOffPqW = kOffPqE + 4 * kCap;             // u32[kCap]
+constexpr uint32_t kOffPqM = kOffPqW + 4 * kCap;             // u32[kCap] nu|rho<<10|j<<20
+constexpr uint32_t kOffMark = kOffPqM + 4 * kCap;            // i32[64]
 constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits, u64[k] ids
 constexpr uint32_t kQueueBytes = kOffBins;
 constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
@@ -317,7 +329,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // Called by all 64 lanes; the `act` lanes carry an area.  Region
                 // and area rounds run only while both queues hold fewer than 64
                 // entries, so neither can overflow.
-                auto emit_area = [&](bool act, uint64_t a, double xi, uint32_t rv, uint32_t wv,
+                auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
                                      uint32_t meta, uint32_t X) {
                     const bool has = act && X > 0;
                     double rank = 0.0;
@@ -331,17 +343,17 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     const uint64_t bp = __ballot(pass);
                     const uint64_t bm = __ballot(more);
                     if (pass) {
-                        const uint32_t pos = (pq_head + pq_count + rank_in(bp)) & (kCapP - 1);
+                        const uint32_t pos = ring(pq_head + pq_count + rank_in(bp));
                         at<uint64_t>(wb, kOffPqA, pos) = a;
-                        at<double>(wb, kOffPqX, pos) = xi;
+                        at<uint32_t>(wb, kOffPqE, pos) = ei;
                         at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
                         at<uint32_t>(wb, kOffPqW, pos) = wv;
                         at<uint32_t>(wb, kOffPqM, pos) = meta;
                     }
                     if (more) {
-                        const uint32_t pos = (dq_head + dq_count + rank_in(bm)) & (kCapD - 1);
+                        const uint32_t pos = ring(dq_head + dq_count + rank_in(bm));
                         at<uint64_t>(wb, kOffDqA, pos) = a;
-                        at<double>(wb, kOffDqX, pos) = xi;
+                        at<uint32_t>(wb, kOffDqE, pos) = ei;
                         at<uint32_t>(wb, kOffDqR, pos) = rv;
                         at<uint32_t>(wb, kOffDqW, pos) = wv;
                         at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25) | (1u << 20);
@@ -352,13 +364,13 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 
                 for (;;) {
                     wave_sync();
-                    if (pq_count >= 64 || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
+                    if (pq_count > kTrig || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- accept round ----------------
                         const uint32_t m = pq_count < 64 ? pq_count : 64;
                         // lanes past m reread the last entry and stay inactive
-                        const uint32_t pos = (pq_head + ((uint32_t)lane < m ? (uint32_t)lane : m - 1)) & (kCapP - 1);
+                        const uint32_t pos = ring(pq_head + ((uint32_t)lane < m ? (uint32_t)lane : m - 1));
                         const uint64_t a = at<uint64_t>(wb, kOffPqA, pos);
-                        const double xi = at<double>(wb, kOffPqX, pos);
+                        const double xi = wts[lo + at<uint32_t>(wb, kOffPqE, pos)];
                         const uint32_t wv = at<uint32_t>(wb, kOffPqW, pos);
                         const uint32_t meta = at<uint32_t>(wb, kOffPqM, pos);
                         const uint64_t rb = at<uint64_t>(wb, kOffPqRank, pos);
@@ -374,15 +386,15 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         } else if (acc) {
                             bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
                         }
-                        pq_head = uni((pq_head + m) & (kCapP - 1));
+                        pq_head = uni(ring(pq_head + m));
                         pq_count = uni(pq_count - m);
-                    } else if (dq_count >= 64 || (dq_count > 0 && rq_count == 0 && !have_chunk)) {
+                    } else if (dq_count > kTrig || (dq_count > 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- dart round ----------------
                         const uint32_t m = dq_count < 64 ? dq_count : 64;
                         const bool act = (uint32_t)lane < m;
-                        const uint32_t rpos = (dq_head + (act ? (uint32_t)lane : m - 1)) & (kCapD - 1);
+                        const uint32_t rpos = ring(dq_head + (act ? (uint32_t)lane : m - 1));
                         const uint64_t a = at<uint64_t>(wb, kOffDqA, rpos);
-                        const double xi = at<double>(wb, kOffDqX, rpos);
+                        const uint32_t ei = at<uint32_t>(wb, kOffDqE, rpos);
                         const uint32_t rv = at<uint32_t>(wb, kOffDqR, rpos);
                         const uint32_t wv = at<uint32_t>(wb, kOffDqW, rpos);
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
@@ -396,31 +408,31 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint64_t bm = __ballot(more);
                         wave_sync();  // every entry of the round is read before any write
                         if (pass) {
-                            const uint32_t pos = (pq_head + pq_count + rank_in(bp)) & (kCapP - 1);
+                            const uint32_t pos = ring(pq_head + pq_count + rank_in(bp));
                             at<uint64_t>(wb, kOffPqA, pos) = a;
-                            at<double>(wb, kOffPqX, pos) = xi;
+                            at<uint32_t>(wb, kOffPqE, pos) = ei;
                             at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
                             at<uint32_t>(wb, kOffPqW, pos) = wv;
                             at<uint32_t>(wb, kOffPqM, pos) = meta & ((1u << 25) - 1);
                         }
                         const uint32_t dq_left = dq_count - m;
                         if (more) {
-                            const uint32_t pos = (dq_head + m + dq_left + rank_in(bm)) & (kCapD - 1);
+                            const uint32_t pos = ring(dq_head + m + dq_left + rank_in(bm));
                             at<uint64_t>(wb, kOffDqA, pos) = a;
-                            at<double>(wb, kOffDqX, pos) = xi;
+                            at<uint32_t>(wb, kOffDqE, pos) = ei;
                             at<uint32_t>(wb, kOffDqR, pos) = rv;
                             at<uint32_t>(wb, kOffDqW, pos) = wv;
                             at<uint32_t>(wb, kOffDqM, pos) = meta + (1u << 20);
                         }
                         pq_count = uni(pq_count + (uint32_t)__popcll(bp));
-                        dq_head = uni((dq_head + m) & (kCapD - 1));
+                        dq_head = uni(ring(dq_head + m));
                         dq_count = uni(dq_left + (uint32_t)__popcll(bm));
-                    } else if (rq_pending >= 64 || rq_count >= 64 || (rq_count > 0 && !have_chunk)) {
+                    } else if (rq_pending >= 64 || rq_count > kTrig || (rq_count > 0 && !have_chunk)) {
                         // ---------------- area round ----------------
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
                         if ((uint32_t)lane < n_items) {
-                            const uint32_t ip = (rq_head + lane) & (kCapR - 1);
+                            const uint32_t ip = ring(rq_head + lane);
                             na = at<uint32_t>(wb, kOffRqNa, ip);
                             first = at<uint32_t>(wb, kOffRqFirst, ip);
                             c = na - first;
@@ -445,11 +457,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const bool act = (uint32_t)lane < m;
                         uint32_t X = 0, wv = 0, rv = 0, meta = 0;
                         uint64_t a = 0;
-                        double xi = 0.0;
+                        uint32_t ei = 0;
                         if (act) {
-                            const uint32_t ip = (rq_head + (uint32_t)src) & (kCapR - 1);
+                            const uint32_t ip = ring(rq_head + (uint32_t)src);
                             const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
-                            xi = at<double>(wb, kOffRqX, ip);
+                            ei = at<uint32_t>(wb, kOffRqE, ip);
                             const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
                             const uint32_t nai = at<uint32_t>(wb, kOffRqNa, ip);
                             meta = at<uint32_t>(wb, kOffRqM, ip);
@@ -464,17 +476,17 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             a = mix64(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = poisson_fast(C, sPois, a);
                         }
-                        emit_area(act, a, xi, rv, wv, meta, X);
+                        emit_area(act, a, ei, rv, wv, meta, X);
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
                         const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
                         const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
                         if (last_local + 1 == last_na) {
-                            rq_head = uni((rq_head + last_src + 1) & (kCapR - 1));
+                            rq_head = uni(ring(rq_head + last_src + 1));
                             rq_count = uni(rq_count - (last_src + 1));
                         } else {
-                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, (rq_head + last_src) & (kCapR - 1)) = last_local + 1;
-                            rq_head = uni((rq_head + last_src) & (kCapR - 1));
+                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, ring(rq_head + last_src)) = last_local + 1;
+                            rq_head = uni(ring(rq_head + last_src));
                             rq_count = uni(rq_count - last_src);
                         }
                         rq_pending = rq_pending > m ? uni(rq_pending - m) : 0u;
@@ -534,13 +546,14 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             X = poisson_fast(C, sPois, a);
                             rest = nau - 1;
                         }
-                        emit_area(act, a, x, 0u, 0u, meta, X);
+                        const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
+                        emit_area(act, a, e, 0u, 0u, meta, X);
                         const bool push_r = act && rest > 0;
                         const uint64_t br = __ballot(push_r);
                         if (push_r) {
-                            const uint32_t pos = (rq_head + rq_count + rank_in(br)) & (kCapR - 1);
+                            const uint32_t pos = ring(rq_head + rq_count + rank_in(br));
                             at<uint64_t>(wb, kOffRqG, pos) = g;
-                            at<double>(wb, kOffRqX, pos) = x;
+                            at<uint32_t>(wb, kOffRqE, pos) = e;
                             at<uint32_t>(wb, kOffRqRc, pos) = rcu;
                             at<uint32_t>(wb, kOffRqNa, pos) = nau;
                             at<uint32_t>(wb, kOffRqFirst, pos) = 1;
@@ -791,11 +804,24 @@ hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, 
     return hipGetLastError();
 }
 
+// Waves per block: the count (1..4, at most 64 KiB of LDS per block) that
+// keeps the most waves resident in a CU's 160 KiB of LDS; ties go to the
+// larger block, which shares one copy of the tables.
 int fast_waves(bool lsh, int k, int K)
 {
+    constexpr size_t kLdsPerCu = 160 * 1024;
     const size_t per = wave_lds_bytes(lsh, k, K);
-    int w = (int)((65536 - kTablesBytes) / per);
-    return w < 1 ? 1 : (w > 4 ? 4 : w);
+    int best = 1, best_resident = 0;
+    for (int w = 1; w <= 4; ++w) {
+        const size_t block = kTablesBytes + (size_t)w * per;
+        if (block > 65536) break;
+        const int resident = w * (int)(kLdsPerCu / block);
+        if (resident >= best_resident) {
+            best = w;
+            best_resident = resident;
+        }
+    }
+    return best;
 }
 
 size_t fast_lds(bool lsh, int k, int K, int waves)
