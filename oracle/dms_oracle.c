@@ -410,3 +410,75 @@ int dmso_lsh_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr,
     }
     return DMSO_OK;
 }
+
+/* qsort order of darts: (rank, id hash) ascending. */
+static int cmp_dart(const void* pa, const void* pb)
+{
+    const dmso_dart* a = (const dmso_dart*)pa;
+    const dmso_dart* b = (const dmso_dart*)pb;
+    if (dart_less(a->rank, a->s, b->rank, b->s)) return -1;
+    if (dart_less(b->rank, b->s, a->rank, a->s)) return 1;
+    return 0;
+}
+
+/*
+ * Bottom-k sketch for one set (Section 3, bottom-k minhash): DartHash_t with
+ * t = k (the caller passes P->t = k), phi following the schedule until the
+ * darts of rank <= tau hold at least k distinct ones; the sketch is the k
+ * smallest by (rank, id hash), ascending.  A dart met twice (a repeated
+ * element id) counts once.
+ */
+int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t* idx,
+                     const double* x, uint64_t* out_s, double* out_rank, double* phi_final)
+{
+    double S;
+    int st = check_row(nnz, x, &S);
+    if (st != DMSO_OK) return st;
+    double phi = P->phi0;
+    for (;;) {
+        if (phi > P->phi_max) return DMSO_RANGE;
+        dart_list L = {0, 0, 0};
+        dmso_counters c;
+        memset(&c, 0, sizeof c);
+        st = darthash(P, nnz, idx, x, phi / S, &L, &c);
+        if (st != DMSO_OK) { free(L.d); return st; }
+        if (L.n > 1) qsort(L.d, (size_t)L.n, sizeof(dmso_dart), cmp_dart);
+        int64_t distinct = 0;
+        for (int64_t n = 0; n < L.n; n++) {
+            if (distinct > 0 && L.d[n].rank == L.d[distinct - 1].rank && L.d[n].s == L.d[distinct - 1].s)
+                continue;
+            L.d[distinct++] = L.d[n];
+        }
+        if (distinct >= k) {
+            for (int32_t m = 0; m < k; m++) {
+                out_s[m] = L.d[m].s;
+                out_rank[m] = L.d[m].rank;
+            }
+            *phi_final = phi;
+            free(L.d);
+            return DMSO_OK;
+        }
+        free(L.d);
+        phi = next_phi(P, phi);
+    }
+}
+
+/* Batched bottom-k sketches; non-OK sets get s = ~0 and rank = +inf. */
+int dmso_bottomk_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr,
+                     const int32_t* idx, const double* x, int32_t k, uint64_t* out_s,
+                     double* out_rank, int8_t* out_status)
+{
+    for (int64_t q = 0; q < n_sets; q++) {
+        int64_t b0 = row_ptr[q], b1 = row_ptr[q + 1];
+        double phi = 0.0;
+        int st = dmso_bottomk_set(P, k, b1 - b0, idx + b0, x + b0, out_s + q * k, out_rank + q * k, &phi);
+        if (st == DMSO_NOMEM) return DMSO_NOMEM;
+        if (out_status) out_status[q] = (int8_t)st;
+        if (st != DMSO_OK)
+            for (int32_t m = 0; m < k; m++) {
+                out_s[q * k + m] = ~0ULL;
+                out_rank[q * k + m] = INFINITY;
+            }
+    }
+    return DMSO_OK;
+}

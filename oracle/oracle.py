@@ -187,6 +187,10 @@ def lib():
                                    vp, vp, vp, vp, vp, P(ctypes.c_double)]
         L.dmso_lsh_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32,
                                    ctypes.c_int32, vp, vp]
+        L.dmso_bottomk_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, vp]
+        L.dmso_bottomk_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+        for f in ("dmso_bottomk_set", "dmso_bottomk_csr"):
+            getattr(L, f).restype = ctypes.c_int
         for f in ("dmso_darthash", "dmso_minhash_set", "dmso_sketch_csr", "dmso_lsh_set",
                   "dmso_lsh_csr"):
             getattr(L, f).restype = ctypes.c_int
@@ -319,6 +323,53 @@ def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
     if st != 0:
         raise MemoryError("oracle out of memory")
     return dict(keys=keys, status=status)
+
+
+def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE):
+    """Bottom-k sketch of one set (Section 3): the k first darts hitting x, with
+    DartHash at t = k.  Returns (status, s[k] uint64, rank[k] float64, phi)."""
+    P = make_params(seed, k, phi0, schedule)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    s = np.zeros(k, dtype=np.uint64)
+    r = np.zeros(k, dtype=np.float64)
+    phi = ctypes.c_double(0.0)
+    st = lib().dmso_bottomk_set(ctypes.byref(P), k, len(idx), _ptr(idx), _ptr(w), _ptr(s), _ptr(r),
+                                ctypes.byref(phi))
+    return st, s, r, phi.value
+
+
+def bottomk_csr(row_ptr, idx, w, k: int, seed: int, phi0: float = 1.0,
+                schedule: int = SCHED_PLUS_ONE):
+    """Bottom-k sketches of every row: dict s [n,k] uint64, rank [n,k] float64,
+    u32 [n,k] (low 32 bits of s), status [n] int8."""
+    rp, idx, w = _csr(row_ptr, idx, w)
+    n = len(rp) - 1
+    P = make_params(seed, k, phi0, schedule)
+    s = np.zeros((n, k), dtype=np.uint64)
+    r = np.zeros((n, k), dtype=np.float64)
+    st = np.zeros(n, dtype=np.int8)
+    rc = lib().dmso_bottomk_csr(ctypes.byref(P), n, _ptr(rp), _ptr(idx), _ptr(w), k, _ptr(s), _ptr(r),
+                                _ptr(st))
+    if rc != 0:
+        raise MemoryError("dmso_bottomk_csr")
+    return {"s": s, "rank": r, "u32": (s & np.uint64(0xFFFFFFFF)).astype(np.uint32), "status": st}
+
+
+def jaccard_est_bottomk(rank_a, s_a, rank_b, s_b):
+    """Bottom-k estimate (the bottom-k sketch estimator of the paper's reference
+    for it): among the k smallest darts of the union of the two sketches, the
+    fraction that lies in both.  Darts are (rank, s) pairs; rows are pairs."""
+    rank_a, rank_b = np.asarray(rank_a, np.float64), np.asarray(rank_b, np.float64)
+    s_a, s_b = np.asarray(s_a, np.uint64), np.asarray(s_b, np.uint64)
+    n, k = rank_a.shape
+    out = np.zeros(n, dtype=np.float64)
+    for p in range(n):
+        A = set(zip(rank_a[p].tolist(), s_a[p].tolist()))
+        B = set(zip(rank_b[p].tolist(), s_b[p].tolist()))
+        union = sorted(A | B)[:k]
+        out[p] = sum(1 for d in union if d in A and d in B) / k
+    return out
 
 
 # --------------------------------------------------------------------------
