@@ -116,13 +116,15 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
 
 
 def secondary_runs(ctx, torch, steps=3):
-    """Throughput of the other two batch workloads (k = 1024 uneven batching and
-    (L,K) = (64,8) LSH keys), each checked bit for bit on a row sample."""
+    """Throughput of the other batch workloads (k = 1024 uneven batching,
+    (L,K) = (64,8) LSH keys, and bottom-k sketches with k = 256 of the main
+    batch), each checked bit for bit on a row sample."""
     from oracle import oracle as O
     from paper_2005_11547_amd import to_device
     res = {}
     for name, gen, kind in (("uneven_k1024", WL.uneven_k1024, "sketch"),
-                            ("lsh_L64K8", WL.lsh_L64K8, "lsh")):
+                            ("lsh_L64K8", WL.lsh_L64K8, "lsh"),
+                            ("bottomk_k256", WL.batch_k256, "bottomk")):
         rp, idx, w = gen()
         n = len(rp) - 1
         d = to_device(rp, idx, w)
@@ -131,10 +133,15 @@ def secondary_runs(ctx, torch, steps=3):
             bits = torch.empty((n, 16), dtype=torch.int64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
             run = lambda: ctx.dms_sketch_csr(n, d[0], d[1], d[2], 1024, out, bits, st)
-        else:
+        elif kind == "lsh":
             out = torch.empty((n, 64), dtype=torch.int64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
             run = lambda: ctx.dms_lsh_keys(n, d[0], d[1], d[2], 64, 8, out, st)
+        else:
+            out = torch.empty((n, 256), dtype=torch.int64, device="cuda")
+            rk = torch.empty((n, 256), dtype=torch.float64, device="cuda")
+            st = torch.empty(n, dtype=torch.int8, device="cuda")
+            run = lambda: ctx.dms_bottomk(n, d[0], d[1], d[2], 256, out, rk, st)
         run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -152,13 +159,67 @@ def secondary_runs(ctx, torch, steps=3):
         if kind == "sketch":
             ref = O.sketch_csr(sub_rp, sub_idx, sub_w, 1024, WL.HASH_SEED)["u32"]
             exact = bool(np.array_equal(got.view(np.uint32), ref))
-        else:
+        elif kind == "lsh":
             ref = O.lsh_csr(sub_rp, sub_idx, sub_w, 64, 8, WL.HASH_SEED)["keys"]
             exact = bool(np.array_equal(got.view(np.uint64), ref))
+        else:
+            ref = O.bottomk_csr(sub_rp, sub_idx, sub_w, 256, WL.HASH_SEED)
+            exact = bool(np.array_equal(got.view(np.uint64), ref["s"]) and
+                         np.array_equal(rk[torch.from_numpy(rows).cuda()].cpu().numpy(), ref["rank"]))
         res[name] = {"sets_per_s": n / (ms * 1e-3), "nnz_per_s": float(rp[-1]) / (ms * 1e-3),
                      "ms_per_step": ms, "n_sets": n, "bit_exact_sample": {"sets_checked": 200, "exact": exact}}
         log(f"{name}: {res[name]}")
         del d, out
+    return res
+
+
+def fingerprint_runs(ctx, torch, out_u32, k, bits=8, steps=5):
+    """b-bit fingerprints of the main batch's minhashes: pack, the b-bit
+    estimate over row pairs (2i, 2i+1), and the unary map.  All three are HBM
+    bound: GB/s of their algorithmic bytes against the 8 TB/s peak, each checked
+    bit for bit on a row sample."""
+    from oracle import oracle as O
+    n = out_u32.shape[0]
+    words = (k * bits + 63) // 64
+    packed = torch.empty((n, words), dtype=torch.int64, device="cuda")
+    n_pairs = n // 2
+    est = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
+    uidx = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    pa, pb = packed[0:2 * n_pairs:2], packed[1:2 * n_pairs:2]
+    ea, eb = pa.contiguous(), pb.contiguous()
+    runs = {
+        "pack": (lambda: ctx.dms_bbit_pack(n, out_u32, k, bits, packed), n * (4.0 * k + 8.0 * words)),
+        "estimate": (lambda: ctx.dms_jaccard_est_bbit(n_pairs, ea, eb, k, bits, est),
+                     n_pairs * (16.0 * words + 8.0)),
+        "unary_map": (lambda: ctx.dms_unary_map(n, out_u32, k, bits, uidx), n * 8.0 * k),
+    }
+    res = {"bits": bits, "n_sets": n, "k": k}
+    for name, (fn, nbytes) in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        if name == "pack":  # the estimate reads the packed rows
+            ea.copy_(packed[0:2 * n_pairs:2]); eb.copy_(packed[1:2 * n_pairs:2])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+    rows = np.linspace(0, n_pairs - 1, 200).astype(np.int64)
+    ra = torch.from_numpy(2 * rows).cuda()
+    ua = out_u32[ra].cpu().numpy().view(np.uint32)
+    ub = out_u32[ra + 1].cpu().numpy().view(np.uint32)
+    ref_pa = O.bbit_pack(ua, bits)
+    ok = np.array_equal(packed[ra].cpu().numpy().view(np.uint64), ref_pa)
+    ok &= np.array_equal(est[torch.from_numpy(rows).cuda()].cpu().numpy(),
+                         O.jaccard_est_bbit(ref_pa, O.bbit_pack(ub, bits), k, bits))
+    ok &= np.array_equal(uidx[ra].cpu().numpy(), O.unary_map(ua, bits)[0])
+    res["bit_exact_sample"] = {"rows_checked": int(len(rows)), "exact": bool(ok)}
+    log(f"fingerprints: {res}")
+    del packed, est, uidx, ea, eb
     return res
 
 
@@ -376,7 +437,9 @@ def main():
         log(f"stream copy of {nb} bytes: {result['roofline']['hbm_copy_gbs']:.0f} GB/s (read+write)")
         del src, dst
     if args.secondary and args.workload == "batch_k256":
+        fp = fingerprint_runs(ctx, torch, out_u32, k)
         result["secondary"] = secondary_runs(ctx, torch)
+        result["secondary"]["bbit_b8"] = fp
     if args.serving_seconds > 0:
         result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db)
     print(json.dumps(result), flush=True)

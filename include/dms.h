@@ -54,6 +54,7 @@ typedef int32_t dms_status;
                                wavefronts, one part of at most this many nonzeros each
                                (default 4096; 0 disables).  The call then reads two counts back
                                from the device before its main launch. */
+#define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
 
 /* Formats of dms_jaccard_est. */
 #define DMS_FMT_U32 0  /* k uint32 minhash values per set */
@@ -135,6 +136,33 @@ dms_status dms_lsh_keys(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, con
  */
 dms_status dms_jaccard_est(dms_ctx ctx, int64_t n_pairs, const void* a, const void* b, int32_t k,
                            int32_t format, double* out);
+
+/*
+ * Bottom-k sketch (Section 3, bottom-k minhash): DartHash with t = k, phi
+ * doubling from DMS_OPT_BOTTOMK_PHI0 until the darts of rank <= tau hold at
+ * least k distinct ones; row s's sketch is its k darts of smallest (rank, id
+ * hash), ascending.  A dart met twice (a repeated element id) counts once.
+ *   row_ptr, idx, w  as for dms_sketch_csr
+ *   out_s      device uint64[n_sets*k]  id hashes (~0 for a set whose status is not OK)
+ *   out_rank   device float64[n_sets*k] or NULL (+inf for such a set)
+ *   out_status device int8[n_sets] or NULL
+ *   k 1..1024
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_bottomk(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                       const double* w, int32_t k, uint64_t* out_s, double* out_rank,
+                       int8_t* out_status);
+
+/*
+ * Jaccard estimate from two bottom-k sketches (dms_bottomk layout, both with
+ * status OK): out[p] = (number of the k first darts of the union of the two
+ * sketches that lie in both) / k.  Darts are equal when rank and id hash are.
+ *   rank_a, rank_b device float64[n_pairs*k]; s_a, s_b device uint64[n_pairs*k]
+ *   out device float64[n_pairs]; k 1..1024
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_jaccard_est_bottomk(dms_ctx ctx, int64_t n_pairs, const double* rank_a, const uint64_t* s_a,
+                                   const double* rank_b, const uint64_t* s_b, int32_t k, double* out);
 
 /*
  * b-bit fingerprints (Section 1.1, similarity estimation): the fingerprint of

@@ -25,9 +25,15 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
                               unsigned long long* counter, int blocks, hipStream_t st);
-int fast_waves(bool lsh, int k, int K);
-size_t fast_lds(bool lsh, int k, int K, int waves);
-const void* fast_kernel_address(bool lsh);
+int fast_waves(int mode, int k, int K);
+size_t fast_lds(int mode, int k, int K, int waves);
+const void* fast_kernel_address(int mode);
+hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint64_t* out_s,
+                               double* out_rank, int8_t* out_status, double phi0, double phi_max,
+                               unsigned long long* counter, int blocks, hipStream_t st);
+hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
+                                  const uint64_t* sb, int k, double* out, hipStream_t st);
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                     const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                     uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
@@ -82,6 +88,7 @@ struct dms_ctx_s {
     size_t partial_bytes = 0;
     double phi0 = 1.0;
     double lsh_phi0 = 3.0;
+    double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
     std::string err;
@@ -151,12 +158,12 @@ dms_status grow(dms_ctx c, void** buf, size_t* have, size_t need)
 }
 
 // Blocks of the persistent kernel that fit on the device at once.
-int resident_blocks(dms_ctx c, bool lsh, int k, int K)
+int resident_blocks(dms_ctx c, int mode, int k, int K)
 {
-    const int waves = dms::fast_waves(lsh, k, K);
+    const int waves = dms::fast_waves(mode, k, K);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(lsh), 64 * waves,
-                                                     dms::fast_lds(lsh, k, K, waves)) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(mode), 64 * waves,
+                                                     dms::fast_lds(mode, k, K, waves)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu * c->n_cu;
@@ -248,10 +255,12 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
         return DMS_OK;
     case DMS_OPT_PHI0:
     case DMS_OPT_LSH_PHI0:
+    case DMS_OPT_BOTTOMK_PHI0:
     case DMS_OPT_PHI_MAX:
         if (!(v > 0.0) || std::isinf(v)) return fail(c, DMS_EINVAL, "phi must be positive and finite");
         if (opt == DMS_OPT_PHI0) c->phi0 = v;
         else if (opt == DMS_OPT_LSH_PHI0) c->lsh_phi0 = v;
+        else if (opt == DMS_OPT_BOTTOMK_PHI0) c->bottomk_phi0 = v;
         else c->phi_max = v;
         return DMS_OK;
     default:
@@ -266,6 +275,7 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_ENGINE: *v = c->engine; return DMS_OK;
     case DMS_OPT_PHI0: *v = c->phi0; return DMS_OK;
     case DMS_OPT_LSH_PHI0: *v = c->lsh_phi0; return DMS_OK;
+    case DMS_OPT_BOTTOMK_PHI0: *v = c->bottomk_phi0; return DMS_OK;
     case DMS_OPT_PHI_MAX: *v = c->phi_max; return DMS_OK;
     case DMS_OPT_SPLIT_NNZ: *v = c->split_nnz; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
@@ -289,7 +299,7 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     hipError_t e;
     // the flattened engine keeps its queues and k buckets in one block's LDS;
     // beyond 64 KiB the plain engine serves the call
-    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(false, k, 1, 1) > 65536) {
+    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeMinhash, k, 1, 1) > 65536) {
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                      out_status, out_s, out_rank, c->phi0, c->phi_max, c->stream);
     } else {
@@ -318,10 +328,46 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         }
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
-                                          c->counter, resident_blocks(c, false, k, 1), c->parts,
+                                          c->counter, resident_blocks(c, dms::kModeMinhash, k, 1), c->parts,
                                           n_parts, c->heavy, c->partial, split, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
+    return DMS_OK;
+}
+
+dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                       const double* w, int32_t k, uint64_t* out_s, double* out_rank, int8_t* out_status)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 0) return fail(c, DMS_EINVAL, "n_sets < 0");
+    if (k < 1 || k > 1024) return fail(c, DMS_EINVAL, "k = %d outside 1..1024", k);
+    if (n_sets == 0) return DMS_OK;
+    if (!row_ptr || !idx || !w || !out_s) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    const dms::SpecTables* sp = nullptr;
+    dms_status st = spec_for(c, (uint32_t)k, &sp);  // t = k
+    if (st != DMS_OK) return st;
+    // phi0 = 1 + 4/sqrt(k) finds k darts in the first pass but for a 4-sigma shortfall
+    const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 4.0 / std::sqrt((double)k);
+    hipError_t e = dms::launch_bottomk_fast(sp, n_sets, row_ptr, idx, w, k, out_s, out_rank, out_status,
+                                            phi0, c->phi_max, c->counter,
+                                            resident_blocks(c, dms::kModeBottomK, k, 1), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "bottom-k launch");
+    return DMS_OK;
+}
+
+dms_status dms_jaccard_est_bottomk(dms_ctx c, int64_t n_pairs, const double* rank_a, const uint64_t* s_a,
+                                   const double* rank_b, const uint64_t* s_b, int32_t k, double* out)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_pairs < 0 || k < 1 || k > 1024) return fail(c, DMS_EINVAL, "bad n_pairs or k");
+    if (n_pairs == 0) return DMS_OK;
+    if (!rank_a || !s_a || !rank_b || !s_b || !out) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipError_t e = dms::launch_bottomk_jaccard(n_pairs, rank_a, s_a, rank_b, s_b, k, out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "bottom-k jaccard launch");
     return DMS_OK;
 }
 
@@ -343,12 +389,12 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     dms_status st = spec_for(c, (uint32_t)(L * K), &sp);
     if (st != DMS_OK) return st;
     hipError_t e;
-    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(true, L, K, 1) > 65536) {
+    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeLsh, L, K, 1) > 65536) {
         e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
                                   c->lsh_phi0, c->phi_max, c->stream);
     } else {
         e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
-                                 c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, true, L, K),
+                                 c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::kModeLsh, L, K),
                                  c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");

@@ -33,6 +33,9 @@ bool make_spec(uint64_t seed, uint32_t t, SpecTables* sp);
 double corner_w(const SpecTables& sp, int nu);
 double corner_r(const SpecTables& sp, int rho);
 
+// Sinks of the fast kernel: k bucket minima, (L,K) LSH tables, bottom-k buffer.
+enum FastMode : int { kModeMinhash = 0, kModeLsh = 1, kModeBottomK = 2 };
+
 // Per-set status values written to out_status.
 enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3 };
 

@@ -120,15 +120,28 @@ constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits
 constexpr uint32_t kQueueBytes = kOffBins;
 constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
 
-// Bytes of the result area after the queues: k bucket minima (minhash) or L
-// sorted lists of K darts plus counts and owner slots (LSH).
-__host__ __device__ constexpr size_t sink_bytes(bool lsh, int k, int K)
+// Dart buffer of a bottom-k wave: a power of two of at least 2k entries with
+// at least k + 64 of them, so that after a compaction (at most k entries kept)
+// a whole round of accepted darts always fits.
+__host__ __device__ constexpr uint32_t bk_cap(int k)
 {
-    return lsh ? (size_t)16 * k * K + (size_t)8 * k : (size_t)16 * k;
+    uint32_t need = (uint32_t)(2 * k > k + 64 ? 2 * k : k + 64), c = 64;
+    while (c < need) c <<= 1;
+    return c;
 }
-__host__ __device__ constexpr size_t wave_lds_bytes(bool lsh, int k, int K)
+
+// Bytes of the result area after the queues: k bucket minima (minhash), L
+// sorted lists of K darts plus counts and owner slots (LSH), or the dart
+// buffer (bottom-k).
+__host__ __device__ constexpr size_t sink_bytes(int mode, int k, int K)
 {
-    return kQueueBytes + sink_bytes(lsh, k, K);
+    return mode == kModeLsh ? (size_t)16 * k * K + (size_t)8 * k
+         : mode == kModeBottomK ? (size_t)16 * bk_cap(k)
+                                : (size_t)16 * k;
+}
+__host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
+{
+    return kQueueBytes + sink_bytes(mode, k, K);
 }
 
 // (L,K) LSH tables of one wave: table l holds cnt[l] <= K darts sorted by
@@ -224,10 +237,11 @@ struct Part {
     int32_t index;
 };
 
-// Persistent flattened DartMinHash (LSH = false: k buckets keep their
-// minimum) or (L,K) LSH (LSH = true: k = L tables keep their K smallest darts).
-// Each wave repeatedly takes the next set index from *next_set.
-template <bool LSH>
+// Persistent flattened DartHash with one of three sinks: DartMinHash (k
+// buckets keep their minimum), (L,K) LSH (k = L tables keep their K smallest
+// darts) or the bottom-k sketch (a buffer of darts, sorted and cut to the k
+// smallest).  Each wave repeatedly takes the next set index from *next_set.
+template <int MODE>
 __global__ void __launch_bounds__(256)
 fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __restrict__ rp,
             const int32_t* __restrict__ idx, const double* __restrict__ wts, int k, int K,
@@ -236,6 +250,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             unsigned long long* next_set, const Part* __restrict__ parts, int64_t n_parts,
             HeavySet* heavy, uint64_t* partial, int64_t split)
 {
+    constexpr bool LSH = MODE == kModeLsh;
+    constexpr bool BK = MODE == kModeBottomK;
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
     double* sR = sW + kTable;
@@ -252,9 +268,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(LSH, k, K);
+    unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(MODE, k, K);
     uint64_t* const bin_rank = reinterpret_cast<uint64_t*>(wb + kOffBins);
-    uint64_t* const bin_s = bin_rank + (LSH ? k * K : k);
+    uint64_t* const bin_s = bin_rank + (LSH ? k * K : BK ? (int)bk_cap(k) : k);
     LshTables T;
     T.rank = bin_rank;
     T.sval = bin_s;
@@ -265,6 +281,79 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
     const double u = sp->u;
     const double td = (double)sp->t;
+
+    // Bottom-k buffer: bk_count darts (rank bits, id hash) in bin_rank/bin_s,
+    // and a cutoff: darts at or above it are never needed (k smaller ones are
+    // held) and are not stored.
+    uint32_t bk_count = 0;
+    uint64_t cut_r = ~0ull, cut_s = ~0ull;
+    // Sort the buffer by (rank, id hash), drop repeated darts and keep at most
+    // the k smallest (the k-th becomes the cutoff).  All 64 lanes call it.
+    auto bk_compact = [&]() {
+        const uint32_t n = bk_count;
+        uint32_t N = 64;
+        while (N < n) N <<= 1;
+        for (uint32_t p = n + lane; p < N; p += kWave) {
+            bin_rank[p] = ~0ull;
+            bin_s[p] = ~0ull;
+        }
+        wave_sync();
+        // bitonic sorting network over N entries, ascending
+        for (uint32_t size = 2; size <= N; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = lane; i < N / 2; i += kWave) {
+                    const uint32_t lo = 2 * i - (i & (stride - 1));
+                    const uint32_t hi = lo + stride;
+                    const uint64_t r0 = bin_rank[lo], s0 = bin_s[lo];
+                    const uint64_t r1 = bin_rank[hi], s1 = bin_s[hi];
+                    const bool gt = r0 > r1 || (r0 == r1 && s0 > s1);
+                    const bool lt = r0 < r1 || (r0 == r1 && s0 < s1);
+                    if ((lo & size) == 0 ? gt : lt) {
+                        bin_rank[lo] = r1;
+                        bin_s[lo] = s1;
+                        bin_rank[hi] = r0;
+                        bin_s[hi] = s0;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // in-place removal of repeats, 64 entries at a time; an entry moves
+        // only towards the front, to a slot whose entry is already read
+        uint32_t D = 0;
+        uint64_t prev_r = 0, prev_s = 0;
+        for (uint32_t base = 0; base < n; base += kWave) {
+            const uint32_t p = base + lane;
+            uint64_t r = ~0ull, sv = ~0ull;
+            bool keep = false;
+            if (p < n) {
+                r = bin_rank[p];
+                sv = bin_s[p];
+                const uint64_t pr = lane == 0 ? prev_r : bin_rank[p - 1];
+                const uint64_t ps = lane == 0 ? prev_s : bin_s[p - 1];
+                keep = p == 0 || r != pr || sv != ps;
+            }
+            const int last = (int)((n - base < (uint32_t)kWave ? n - base : (uint32_t)kWave) - 1);
+            prev_r = __shfl(r, last, kWave);
+            prev_s = __shfl(sv, last, kWave);
+            const uint64_t bm = __ballot(keep);
+            wave_sync();
+            if (keep) {
+                const uint32_t q = D + rank_in(bm);
+                bin_rank[q] = r;
+                bin_s[q] = sv;
+            }
+            D = uni(D + (uint32_t)__popcll(bm));
+            wave_sync();
+        }
+        if (D > (uint32_t)k) {
+            D = (uint32_t)k;
+            cut_r = bin_rank[k - 1];
+            cut_s = bin_s[k - 1];
+        }
+        bk_count = D;
+        wave_sync();
+    };
 
     // Runs phi passes over the elements [lo, hi) of a row with ||x||_1 = S,
     // starting at phi (darts of rank <= tau_prev are already in the buckets),
@@ -383,6 +472,20 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         if (acc) s = mix64(a ^ KS ^ j);
                         if (LSH) {
                             T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, lane);
+                        } else if (BK) {
+                            bool keep = acc && (rb < cut_r || (rb == cut_r && s < cut_s));
+                            uint64_t bk = __ballot(keep);
+                            if (bk_count + (uint32_t)__popcll(bk) > bk_cap(k)) {
+                                bk_compact();  // at most k stay, so the round fits afterwards
+                                keep = keep && (rb < cut_r || (rb == cut_r && s < cut_s));
+                                bk = __ballot(keep);
+                            }
+                            if (keep) {
+                                const uint32_t q = bk_count + rank_in(bk);
+                                bin_rank[q] = rb;
+                                bin_s[q] = s;
+                            }
+                            bk_count = uni(bk_count + (uint32_t)__popcll(bk));
                         } else if (acc) {
                             bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
                         }
@@ -576,6 +679,16 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 if (wave_any(range)) { status = kSetRange; break; }
                 wave_sync();
                 if (single) break;
+                if (BK) {
+                    // done once the darts of rank <= tau hold k distinct ones
+                    if (bk_count >= (uint32_t)k) {
+                        bk_compact();
+                        if (bk_count >= (uint32_t)k) break;
+                    }
+                    tau_prev = tau;
+                    phi *= 2.0;
+                    continue;
+                }
                 bool filled = true;
                 if (LSH) {
                     for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
@@ -590,7 +703,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     };
 
     auto clear_buckets = [&]() {
-        if (LSH) {
+        if (BK) {
+            bk_count = 0;
+            cut_r = ~0ull;
+            cut_s = ~0ull;
+        } else if (LSH) {
             for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
         } else {
             for (int j = lane; j < k; j += kWave) {
@@ -607,7 +724,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         if (item >= n_parts + n_sets) break;
         int64_t set;
         int8_t status;
-        if (!LSH && item < n_parts) {
+        if (MODE == kModeMinhash && item < n_parts) {
             // ---- one part of a heavy set ----
             const Part pt = parts[item];
             HeavySet* hs = heavy + pt.heavy;
@@ -658,7 +775,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         } else {
             set = item - n_parts;
             const int64_t b0 = rp[set], b1 = rp[set + 1];
-            if (!LSH && split > 0 && b1 - b0 > split) continue;  // served by its parts
+            if (MODE == kModeMinhash && split > 0 && b1 - b0 > split) continue;  // served by its parts
             const RowInfo ri = scan_row(wts, b0, b1, lane);
             status = ri.status;
             if (status == kSetOk) {
@@ -704,17 +821,17 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
-// Explicit instantiations: the host launches both.
-template __global__ void fast_kernel<false>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
-                                            const double*, int, int, uint32_t*, uint64_t*, int8_t*,
-                                            uint64_t*, double*, uint64_t*, double, double,
-                                            unsigned long long*, const Part*, int64_t, HeavySet*,
+// Explicit instantiations: the host launches all three.
+#define DMS_FAST_KERNEL(M)                                                                        \
+    template __global__ void fast_kernel<M>(const SpecTables*, int64_t, const int64_t*, const int32_t*, \
+                                            const double*, int, int, uint32_t*, uint64_t*, int8_t*,     \
+                                            uint64_t*, double*, uint64_t*, double, double,             \
+                                            unsigned long long*, const Part*, int64_t, HeavySet*,      \
                                             uint64_t*, int64_t);
-template __global__ void fast_kernel<true>(const SpecTables*, int64_t, const int64_t*, const int32_t*,
-                                           const double*, int, int, uint32_t*, uint64_t*, int8_t*,
-                                           uint64_t*, double*, uint64_t*, double, double,
-                                           unsigned long long*, const Part*, int64_t, HeavySet*,
-                                           uint64_t*, int64_t);
+DMS_FAST_KERNEL(kModeMinhash)
+DMS_FAST_KERNEL(kModeLsh)
+DMS_FAST_KERNEL(kModeBottomK)
+#undef DMS_FAST_KERNEL
 
 // Planning.  plan[0] = heavy sets, plan[1] = parts (counting pass); plan[2],
 // plan[3] are the cursors of the filling pass.
@@ -807,10 +924,10 @@ hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, 
 // Waves per block: the count (1..4, at most 64 KiB of LDS per block) that
 // keeps the most waves resident in a CU's 160 KiB of LDS; ties go to the
 // larger block, which shares one copy of the tables.
-int fast_waves(bool lsh, int k, int K)
+int fast_waves(int mode, int k, int K)
 {
     constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t per = wave_lds_bytes(lsh, k, K);
+    const size_t per = wave_lds_bytes(mode, k, K);
     int best = 1, best_resident = 0;
     for (int w = 1; w <= 4; ++w) {
         const size_t block = kTablesBytes + (size_t)w * per;
@@ -824,18 +941,19 @@ int fast_waves(bool lsh, int k, int K)
     return best;
 }
 
-size_t fast_lds(bool lsh, int k, int K, int waves)
+size_t fast_lds(int mode, int k, int K, int waves)
 {
-    return kTablesBytes + (size_t)waves * wave_lds_bytes(lsh, k, K);
+    return kTablesBytes + (size_t)waves * wave_lds_bytes(mode, k, K);
 }
 
-int fast_waves_per_block(int k) { return fast_waves(false, k, 1); }
-size_t fast_lds_bytes(int k, int waves) { return fast_lds(false, k, 1, waves); }
+int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, 1); }
+size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, 1, waves); }
 
-const void* fast_kernel_address(bool lsh)
+const void* fast_kernel_address(int mode)
 {
-    return lsh ? reinterpret_cast<const void*>(&fast_kernel<true>)
-               : reinterpret_cast<const void*>(&fast_kernel<false>);
+    return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh>)
+         : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK>)
+                                : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash>);
 }
 
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
@@ -847,12 +965,12 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves(false, k, 1);
-    const size_t lds = fast_lds(false, k, 1, waves);
+    const int waves = fast_waves(kModeMinhash, k, 1);
+    const size_t lds = fast_lds(kModeMinhash, k, 1, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_parts + n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<false>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    hipLaunchKernelGGL(fast_kernel<kModeMinhash>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
                        (HeavySet*)heavy, partial, split);
@@ -876,16 +994,34 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
                            unsigned long long* counter, int blocks, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves(true, L, K);
-    const size_t lds = fast_lds(true, L, K, waves);
+    const int waves = fast_waves(kModeLsh, L, K);
+    const size_t lds = fast_lds(kModeLsh, L, K, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<true>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    hipLaunchKernelGGL(fast_kernel<kModeLsh>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
                        (const Part*)nullptr, (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr,
                        (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint64_t* out_s,
+                               double* out_rank, int8_t* out_status, double phi0, double phi_max,
+                               unsigned long long* counter, int blocks, hipStream_t st)
+{
+    if (n_sets <= 0) return hipSuccess;
+    const int waves = fast_waves(kModeBottomK, k, 1);
+    const size_t lds = fast_lds(kModeBottomK, k, 1, waves);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    const int64_t need = (n_sets + waves - 1) / waves;
+    if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
+    hipLaunchKernelGGL(fast_kernel<kModeBottomK>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+                       n_sets, rp, idx, w, k, 1, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
+                       out_s, out_rank, (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)nullptr,
+                       (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0);
     return hipGetLastError();
 }
 

@@ -15,14 +15,14 @@ LIB_PATH = os.path.join(HERE, "libdms.so")
 DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
 SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
-OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ = 0, 1, 2, 3, 4
+OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0 = 0, 1, 2, 3, 4, 5
 FMT_U32, FMT_1BIT = 0, 1
 
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
            "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
-           "dms_jaccard_est_bbit", "dms_unary_map"]
+           "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -60,6 +60,8 @@ def lib():
         "dms_lsh_keys": ([vp, i64, vp, vp, vp, i32, i32, vp, vp], i32),
         "dms_jaccard_est": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_bbit_pack": ([vp, i64, vp, i32, i32, vp], i32),
+        "dms_bottomk": ([vp, i64, vp, vp, vp, i32, vp, vp, vp], i32),
+        "dms_jaccard_est_bottomk": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "dms_jaccard_est_bbit": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_unary_map": ([vp, i64, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "dms_hamming_topk": ([vp, vp, i64, i32, vp, i64, i32, vp, vp], i32),
@@ -171,6 +173,16 @@ class Context:
         self._check(lib().dms_jaccard_est(self._h, n_pairs, _ptr(a), _ptr(b), k, fmt, _ptr(out)),
                     "dms_jaccard_est")
 
+    def dms_bottomk(self, n_sets, row_ptr, idx, w, k, out_s, out_rank=None, out_status=None):
+        self._stream()
+        self._check(lib().dms_bottomk(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), k, _ptr(out_s),
+                                      _ptr(out_rank), _ptr(out_status)), "dms_bottomk")
+
+    def dms_jaccard_est_bottomk(self, n_pairs, rank_a, s_a, rank_b, s_b, k, out):
+        self._stream()
+        self._check(lib().dms_jaccard_est_bottomk(self._h, n_pairs, _ptr(rank_a), _ptr(s_a), _ptr(rank_b),
+                                                  _ptr(s_b), k, _ptr(out)), "dms_jaccard_est_bottomk")
+
     def dms_bbit_pack(self, n_sets, minhash, k, bits, out):
         self._stream()
         self._check(lib().dms_bbit_pack(self._h, n_sets, _ptr(minhash), k, bits, _ptr(out)), "dms_bbit_pack")
@@ -233,6 +245,25 @@ class Context:
         torch = self._torch
         out = torch.empty(a.shape[0], dtype=torch.float64, device=a.device)
         self.dms_jaccard_est(a.shape[0], a, b, k, fmt, out)
+        return out
+
+    def bottomk(self, row_ptr, idx, w, k):
+        """Bottom-k sketches: dict s (int64 [n, k], uint64 bits), rank (float64
+        [n, k]) and status (int8 [n])."""
+        torch = self._torch
+        n = row_ptr.numel() - 1
+        dev = row_ptr.device
+        out = dict(s=torch.empty((n, k), dtype=torch.int64, device=dev),
+                   rank=torch.empty((n, k), dtype=torch.float64, device=dev),
+                   status=torch.empty(n, dtype=torch.int8, device=dev))
+        self.dms_bottomk(n, row_ptr, idx, w, k, out["s"], out["rank"], out["status"])
+        return out
+
+    def jaccard_bottomk(self, rank_a, s_a, rank_b, s_b):
+        torch = self._torch
+        n, k = rank_a.shape
+        out = torch.empty(n, dtype=torch.float64, device=rank_a.device)
+        self.dms_jaccard_est_bottomk(n, rank_a, s_a, rank_b, s_b, k, out)
         return out
 
     def bbit_pack(self, minhash, bits):
