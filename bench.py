@@ -62,7 +62,7 @@ def calibrate_mixer(ctx, torch, n_cu):
     return mixers / (ms * 1e-3)
 
 
-def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
+def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=256):
     """The serving workload: Poisson arrivals at `rate`, half sketch-only requests
     (k uniform in {64, 256, 1024}), half 1-bit k = 1024 sketch + top-10 Hamming
     search against a device-resident database of n_db sketched sets; 1% of the
@@ -97,7 +97,7 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
         rows[r] = WL.near_duplicate(rng, db_idx[db_rp[tgt]:db_rp[tgt + 1]], db_w[db_rp[tgt]:db_rp[tgt + 1]], 0.9)
     rp, idx, w = WL.csr_from_rows(rows)
     srv = Server(ctx, db_bits, topk=10, max_batch=512, max_inflight=4, max_batch_nnz=1 << 21,
-                 max_set_nnz=8192)
+                 max_set_nnz=8192, split_nnz=split_nnz)
     log(f"serving: replaying {n_req} requests at {rate:.0f}/s")
     out = srv.replay(arrival, kind, k, rp, idx, w)
     srv.close()
@@ -110,7 +110,7 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0):
            "max_ms": float(lat[-1] * 1e3), "batches": out["stats"]["batches"],
            "mean_batch": out["stats"]["mean_batch"], "db_rows": n_db,
            "search_share": float(kind.mean()), "planted_top1": top1,
-           "trace": f"{seconds:.0f}s after {warm:.0f}s warm-up"}
+           "trace": f"{seconds:.0f}s after {warm:.0f}s warm-up", "split_nnz": split_nnz}
     log(f"serving: {res}")
     return res
 
@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
+    ap.add_argument("--serving-split", type=int, default=256,
+                    help="serving: sets with more nonzeros are shared by several wavefronts (0: never)")
     ap.add_argument("--table1", action="store_true",
                     help="time the paper's Table 1 shapes instead (GPU, oracle, paper) and exit")
     ap.add_argument("--secondary", type=int, default=1,
@@ -441,7 +443,8 @@ def main():
         result["secondary"] = secondary_runs(ctx, torch)
         result["secondary"]["bbit_b8"] = fp
     if args.serving_seconds > 0:
-        result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db)
+        result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db,
+                                        split_nnz=args.serving_split)
     print(json.dumps(result), flush=True)
 
 

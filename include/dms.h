@@ -258,6 +258,8 @@ typedef struct {
     int32_t max_set_nnz;   /* largest request set accepted, <= max_batch_nnz */
     int32_t db_words;      /* words per database row: 16 */
     int32_t topk;          /* neighbours per search, 1..64 */
+    int32_t split_nnz;     /* sets with more nonzeros are shared by several wavefronts,
+                              parts of at most this many each (0: never); 16.. */
 } dms_server_config;
 
 typedef struct dms_server_s* dms_server;

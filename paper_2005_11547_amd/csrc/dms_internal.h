@@ -36,6 +36,27 @@ double corner_r(const SpecTables& sp, int rho);
 // Sinks of the fast kernel: k bucket minima, (L,K) LSH tables, bottom-k buffer.
 enum FastMode : int { kModeMinhash = 0, kModeLsh = 1, kModeBottomK = 2 };
 
+// A set with more nonzeros than the split threshold is cut into parts of at
+// most `split` consecutive nonzeros.  Every part runs one phi pass over its
+// elements into buckets of its own (in HBM); the part that finishes last
+// merges them by the exact (rank, id) minimum and, if a bucket is still empty,
+// carries on with the doubling retry over the whole set.  Minimum is
+// associative and idempotent, so the result equals the one-wave result.
+struct HeavySet {
+    double sum;      // ||x||_1 of the set (positive weights), set by the row scan
+    int64_t set;     // row index within the launch
+    int64_t base;    // index of its first part
+    int32_t parts;
+    int32_t done;    // parts finished (0 at launch)
+    int32_t range;   // a part met an out-of-range index (0 at launch)
+    int32_t status;  // status of the row scan
+};
+struct Part {
+    int64_t set;
+    int32_t heavy;   // index of its HeavySet
+    int32_t index;   // part number within the set
+};
+
 // Per-set status values written to out_status.
 enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3 };
 

@@ -35,6 +35,15 @@ hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64
                                uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                                double* out_rank, double phi0, double phi_max, hipStream_t st);
 size_t fast_lds_bytes(int k, int waves);
+hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                                    double* out_rank, double phi0, double phi_max,
+                                    unsigned long long* counter, int blocks, const void* parts,
+                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
+                                    hipStream_t st);
+hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
+                             hipStream_t st);
 size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
 int hamming_blocks(int64_t n_db, int n_cu);
 hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
@@ -68,6 +77,11 @@ struct Slot {
     int32_t* d_dist = nullptr;
     uint64_t* d_partial = nullptr;
     unsigned long long* d_counter = nullptr;
+    dms::Part* d_parts = nullptr;          // heavy-set plan of the batch
+    dms::HeavySet* d_heavy = nullptr;
+    uint64_t* d_part_buckets = nullptr;    // 2k words per part
+    dms::Part* h_parts = nullptr;
+    dms::HeavySet* h_heavy = nullptr;
     // pinned host staging
     int64_t* h_rp = nullptr;
     int32_t* h_idx = nullptr;
@@ -114,6 +128,8 @@ void free_slot(Slot& s)
     (void)hipFree(s.d_rp); (void)hipFree(s.d_idx); (void)hipFree(s.d_w); (void)hipFree(s.d_u32);
     (void)hipFree(s.d_bits); (void)hipFree(s.d_status); (void)hipFree(s.d_ids);
     (void)hipFree(s.d_dist); (void)hipFree(s.d_partial); (void)hipFree(s.d_counter);
+    (void)hipFree(s.d_parts); (void)hipFree(s.d_heavy); (void)hipFree(s.d_part_buckets);
+    (void)hipHostFree(s.h_parts); (void)hipHostFree(s.h_heavy);
     (void)hipHostFree(s.h_rp); (void)hipHostFree(s.h_idx); (void)hipHostFree(s.h_w);
     (void)hipHostFree(s.h_u32); (void)hipHostFree(s.h_status); (void)hipHostFree(s.h_ids);
     (void)hipHostFree(s.h_dist);
@@ -167,6 +183,7 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
         e = hipMemcpyAsync(s.d_w, s.h_w, nnz * sizeof(double), hipMemcpyHostToDevice, st);
     // one sketch launch per k group
     int64_t row0 = 0;
+    int64_t part_base = 0, part_heavy = 0, bucket_base = 0;  // plan space used by earlier groups
     for (int g = 0; g < 3 && e == hipSuccess; ++g) {
         const int k = kKinds[g];
         int64_t n = 0;
@@ -178,9 +195,51 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
         // 1-bit sketches are needed only for the search queries (k = 1024)
         uint64_t* obits = k == 1024 ? s.d_bits : nullptr;
         if (dms::fast_lds_bytes(k, 1) <= 65536) {
-            e = dms::launch_sketch_fast(sp, n, s.d_rp + row0, s.d_idx, s.d_w, k, o32, obits,
-                                        s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
-                                        dms::ctx_phi_max(S->ctx), s.d_counter + g, 2 * dms::ctx_n_cu(S->ctx), st);
+            // sets above the split threshold are shared by several waves: the
+            // plan is made here from the host copy of the batch
+            const int64_t split = C.split_nnz;
+            int64_t n_parts = 0, n_heavy = 0;
+            if (split > 0) {
+                for (int64_t i = row0; i < row0 + n; ++i) {
+                    const int64_t len = s.h_rp[i + 1] - s.h_rp[i];
+                    if (len <= split) continue;
+                    dms::HeavySet& h = s.h_heavy[part_heavy + n_heavy];
+                    h.sum = 0.0;
+                    h.set = i - row0;
+                    h.base = n_parts;
+                    h.parts = (int32_t)((len + split - 1) / split);
+                    h.done = 0;
+                    h.range = 0;
+                    h.status = 0;
+                    for (int32_t q = 0; q < h.parts; ++q) {
+                        dms::Part& pt = s.h_parts[part_base + n_parts + q];
+                        pt.set = i - row0;
+                        pt.heavy = (int32_t)n_heavy;
+                        pt.index = q;
+                    }
+                    n_parts += h.parts;
+                    ++n_heavy;
+                }
+            }
+            dms::Part* dp = s.d_parts + part_base;
+            dms::HeavySet* dh = s.d_heavy + part_heavy;
+            uint64_t* db = s.d_part_buckets + bucket_base;
+            if (n_parts > 0) {
+                e = hipMemcpyAsync(dp, s.h_parts + part_base, n_parts * sizeof(dms::Part), hipMemcpyHostToDevice, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(dh, s.h_heavy + part_heavy, n_heavy * sizeof(dms::HeavySet),
+                                       hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) e = dms::launch_heavy_scan(n_heavy, s.d_rp + row0, s.d_w, dh, st);
+            }
+            if (e == hipSuccess)
+                e = dms::launch_sketch_fast_split(sp, n, s.d_rp + row0, s.d_idx, s.d_w, k, o32, obits,
+                                                  s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
+                                                  dms::ctx_phi_max(S->ctx), s.d_counter + g,
+                                                  2 * dms::ctx_n_cu(S->ctx), dp, n_parts, dh, db,
+                                                  n_parts > 0 ? split : 0, st);
+            part_base += n_parts;
+            part_heavy += n_heavy;
+            bucket_base += n_parts * 2 * (int64_t)k;
         } else {
             e = dms::launch_sketch_plain(sp, n, s.d_rp + row0, s.d_idx, s.d_w, k, o32, obits,
                                          s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
@@ -219,7 +278,7 @@ dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, const ui
     const dms_server_config& C = *cfg;
     if (C.max_batch < 1 || C.max_batch > 4096 || C.max_inflight < 1 || C.max_inflight > 16 ||
         C.max_batch_nnz < 1 || C.db_words != 16 || C.topk < 1 || C.topk > 64 || C.max_set_nnz < 1 ||
-        C.max_set_nnz > C.max_batch_nnz)
+        C.max_set_nnz > C.max_batch_nnz || C.split_nnz < 0 || (C.split_nnz > 0 && C.split_nnz < 16))
         return DMS_EINVAL;
     hipError_t e = hipSetDevice(dms::ctx_device(ctx));
     if (e != hipSuccess) return DMS_EHIP;
@@ -246,6 +305,14 @@ dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, const ui
         if (e == hipSuccess)
             e = hipMalloc((void**)&s.d_partial, dms::hamming_partial_bytes((int64_t)q, S->hamming_blocks, C.topk) + 16);
         if (e == hipSuccess) e = dev_alloc(&s.d_counter, 4);
+        // the heavy-set plan: at most max_batch heavy sets and nnz/split + max_batch parts
+        const size_t max_parts = C.split_nnz > 0 ? (size_t)(C.max_batch_nnz / C.split_nnz) + rows : 1;
+        const size_t max_heavy = C.split_nnz > 0 ? rows : 1;
+        if (e == hipSuccess) e = dev_alloc(&s.d_parts, max_parts);
+        if (e == hipSuccess) e = dev_alloc(&s.d_heavy, max_heavy);
+        if (e == hipSuccess) e = dev_alloc(&s.d_part_buckets, max_parts * 2 * 1024);
+        if (e == hipSuccess) e = host_alloc(&s.h_parts, max_parts);
+        if (e == hipSuccess) e = host_alloc(&s.h_heavy, max_heavy);
         if (e == hipSuccess) e = host_alloc(&s.h_rp, rows + 1);
         if (e == hipSuccess) e = host_alloc(&s.h_idx, nnz);
         if (e == hipSuccess) e = host_alloc(&s.h_w, nnz);

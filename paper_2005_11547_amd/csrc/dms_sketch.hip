@@ -216,27 +216,6 @@ __device__ __forceinline__ double exact_count(double base, double step, double b
 
 }  // namespace
 
-// A set with more nonzeros than the split threshold is cut into parts of at
-// most `split` consecutive nonzeros.  Every part runs one phi pass over its
-// elements into buckets of its own (in HBM); the part that finishes last
-// merges them by the exact (rank, id) minimum and, if a bucket is still empty,
-// carries on with the doubling retry over the whole set.  Minimum is
-// associative and idempotent, so the result equals the one-wave result.
-struct HeavySet {
-    double sum;      // ||x||_1 of the set (positive weights)
-    int64_t set;
-    int64_t base;    // index of its first part
-    int32_t parts;
-    int32_t done;    // parts finished
-    int32_t range;   // a part met an out-of-range index
-    int32_t status;  // status of the row scan
-};
-struct Part {
-    int64_t set;
-    int32_t heavy;
-    int32_t index;
-};
-
 // Persistent flattened DartHash with one of three sinks: DartMinHash (k
 // buckets keep their minimum), (L,K) LSH (k = L tables keep their K smallest
 // darts) or the bottom-k sketch (a buffer of darts, sorted and cut to the k
@@ -891,6 +870,15 @@ heavy_scan_kernel(int64_t n_heavy, const int64_t* __restrict__ rp, const double*
         heavy[h].sum = ri.sum;
         heavy[h].status = ri.status;
     }
+}
+
+hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
+                             hipStream_t st)
+{
+    if (n_heavy <= 0) return hipSuccess;
+    hipLaunchKernelGGL(heavy_scan_kernel, dim3((unsigned)((n_heavy + 3) / 4)), dim3(256), 0, st, n_heavy,
+                       rp, w, heavy);
+    return hipGetLastError();
 }
 
 __global__ void reset_plan_kernel(unsigned long long* plan)

@@ -32,7 +32,7 @@ _lib = None
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("max_batch_nnz", ctypes.c_int64), ("max_set_nnz", ctypes.c_int32),
-                ("db_words", ctypes.c_int32), ("topk", ctypes.c_int32)]
+                ("db_words", ctypes.c_int32), ("topk", ctypes.c_int32), ("split_nnz", ctypes.c_int32)]
 
 
 class DMSError(RuntimeError):
@@ -303,10 +303,10 @@ class Server:
     database of 1-bit k = 1024 sketches."""
 
     def __init__(self, ctx: Context, db, topk=10, max_batch=256, max_inflight=4,
-                 max_batch_nnz=1 << 20, max_set_nnz=4096):
+                 max_batch_nnz=1 << 20, max_set_nnz=4096, split_nnz=256):
         import numpy as np
         self.ctx, self.db, self.topk = ctx, db, topk
-        cfg = ServerConfig(max_batch, max_inflight, max_batch_nnz, max_set_nnz, 16, topk)
+        cfg = ServerConfig(max_batch, max_inflight, max_batch_nnz, max_set_nnz, 16, topk, split_nnz)
         self._h = ctypes.c_void_p()
         st = lib().dms_server_create(ctx._h, ctypes.byref(cfg), _ptr(db), db.shape[0] if db is not None else 0,
                                      ctypes.byref(self._h))

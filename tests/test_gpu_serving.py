@@ -133,3 +133,19 @@ def test_server_rejects_bad_requests(torch, ctx, served):
     bad_k2 = np.array([64, 64], np.int32)
     with pytest.raises(DMSError):
         served["srv"].replay(arrival[:2], bad_kind, bad_k2, rp[:3], idx[:rp[2]], w[:rp[2]])
+
+
+@pytest.mark.parametrize("split", [0, 16, 100])
+def test_split_threshold_does_not_change_results(torch, ctx, served, split):
+    # sets above the threshold are cut into parts run by several wavefronts
+    # (at 16, nearly every set); the served results may not change
+    from paper_2005_11547_amd import Server
+    arrival, kind, k, rp, idx, w = served["trace"]
+    n = 120
+    srv = Server(ctx, served["db"], topk=10, max_batch=40, max_inflight=2, split_nnz=split)
+    got = srv.replay(arrival[:n] * 0.0, kind[:n], k[:n], rp[:n + 1], idx[:rp[n]], w[:rp[n]])
+    srv.close()
+    for r in range(n):
+        assert np.array_equal(got["sketch"][r], served["out"]["sketch"][r]), (split, r)
+        assert got["status"][r] == served["out"]["status"][r]
+        assert np.array_equal(got["ids"][r], served["out"]["ids"][r])
