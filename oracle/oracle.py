@@ -474,3 +474,120 @@ def unary_map(minhash_u32, b: int):
     n, k = v.shape
     idx = (np.arange(k, dtype=np.int64) << b)[None, :] + v
     return idx.astype(np.int32), 1.0 / math.sqrt(k)
+
+
+# --------------------------------------------------------------------------
+# Weight classes and the LSH index (Section 3, approximate near neighbours)
+# --------------------------------------------------------------------------
+def seq_sum(w) -> float:
+    """||x||_1 summed left to right in binary64 (the order both sides use)."""
+    s = 0.0
+    for v in np.asarray(w, dtype=np.float64).tolist():
+        if v > 0.0:
+            s += v
+    return s
+
+
+def weight_class(w) -> int:
+    """c with ||x||_1 in [2^c, 2^(c+1)) (the paper's weight classes)."""
+    m, e = math.frexp(seq_sum(w))
+    return e - 1
+
+
+def row_ok_for_index(idx, w) -> bool:
+    """Index rows must list strictly increasing ids with finite weights >= 0
+    and some positive weight, inside the supported range."""
+    idx = np.asarray(idx, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    if len(idx) == 0 or np.any(np.diff(idx) <= 0):
+        return False
+    if not np.all(np.isfinite(w)) or np.any(w < 0) or not np.any(w > 0):
+        return False
+    return 2.0 ** -768 <= w.max() <= 2.0 ** 768
+
+
+def weighted_jaccard_merge(ia, wa, ib, wb) -> float:
+    """J(x, y) = sum min / sum max over the union of the two (id-sorted) rows,
+    both sums taken in ascending id order."""
+    ia, ib = np.asarray(ia).tolist(), np.asarray(ib).tolist()
+    wa, wb = np.asarray(wa, np.float64).tolist(), np.asarray(wb, np.float64).tolist()
+    i = j = 0
+    smin = smax = 0.0
+    while i < len(ia) or j < len(ib):
+        if j >= len(ib) or (i < len(ia) and ia[i] < ib[j]):
+            smax += wa[i]
+            i += 1
+        elif i >= len(ia) or ib[j] < ia[i]:
+            smax += wb[j]
+            j += 1
+        else:
+            smin += min(wa[i], wb[j])
+            smax += max(wa[i], wb[j])
+            i += 1
+            j += 1
+    return smin / smax if smax > 0 else 0.0
+
+
+def class_span(j1: float) -> int:
+    """Classes searched on each side of the query's: J >= j1 bounds the norm
+    ratio by 1/j1, i.e. ceil(log2(1/j1)) classes, plus one for the floors."""
+    return int(math.ceil(math.log2(1.0 / j1))) + 1
+
+
+def lsh_index_build(row_ptr, idx, w, L: int, K: int, seed: int):
+    """The index: per set its class and status, and per table l a dict from
+    (class, key of the normalised set) to the ascending ids of the sets there."""
+    rp, idx, w = _csr(row_ptr, idx, w)
+    n = len(rp) - 1
+    cls = np.zeros(n, dtype=np.int32)
+    ok = np.zeros(n, dtype=bool)
+    rows = []
+    for q in range(n):
+        ii, ww = idx[rp[q]:rp[q + 1]], w[rp[q]:rp[q + 1]]
+        ok[q] = row_ok_for_index(ii, ww)
+        if ok[q]:
+            cls[q] = weight_class(ww)
+            rows.append((ii, np.ldexp(ww, -int(cls[q]))))
+        else:
+            rows.append((ii[:0], ww[:0]))
+    nrp = np.zeros(n + 1, dtype=np.int64)
+    nrp[1:] = np.cumsum([len(r[0]) for r in rows])
+    nidx = np.concatenate([r[0] for r in rows]) if n else np.zeros(0, np.int32)
+    nw = np.concatenate([r[1] for r in rows]) if n else np.zeros(0)
+    keys = lsh_csr(nrp, nidx, nw, L, K, seed)["keys"]
+    tables = [dict() for _ in range(L)]
+    for q in range(n):
+        if not ok[q]:
+            continue
+        for l in range(L):
+            tables[l].setdefault((int(cls[q]), int(keys[q, l])), []).append(q)
+    return {"class": cls, "ok": ok, "keys": keys, "tables": tables, "L": L, "K": K, "seed": seed,
+            "rows": (rp, idx, w)}
+
+
+def lsh_index_query(index, q_idx, q_w, j1: float, topn: int):
+    """Near neighbours of one query set: for every class within class_span(j1)
+    of the query's, the query scaled into that class is hashed to its L keys;
+    the union of the matching buckets is verified with the exact weighted
+    Jaccard.  Returns (candidates, [(J, id), ...] of J >= j1, by J descending
+    then id ascending, at most topn)."""
+    if not row_ok_for_index(q_idx, q_w):
+        return 0, []
+    rp, idx, w = index["rows"]
+    cq = weight_class(q_w)
+    span = class_span(j1)
+    cands = set()
+    for c in range(cq - span, cq + span + 1):
+        qs = np.ldexp(np.asarray(q_w, np.float64), -c)
+        st, keys, _, _, _ = lsh_set(q_idx, qs, index["L"], index["K"], index["seed"])
+        if st != 0:
+            continue
+        for l in range(index["L"]):
+            cands.update(index["tables"][l].get((c, int(keys[l])), []))
+    res = []
+    for x in sorted(cands):
+        J = weighted_jaccard_merge(q_idx, q_w, idx[rp[x]:rp[x + 1]], w[rp[x]:rp[x + 1]])
+        if J >= j1:
+            res.append((J, x))
+    res.sort(key=lambda t: (-t[0], t[1]))
+    return len(cands), res[:topn]
