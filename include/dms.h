@@ -39,6 +39,7 @@ typedef int32_t dms_status;
 #define DMS_SET_EMPTY 1   /* no positive weight: the minhash is undefined (J = 0/0) */
 #define DMS_SET_RANGE 2   /* largest weight outside [2^-768, 2^768], or phi beyond its cap */
 #define DMS_SET_INVALID 3 /* a negative, NaN or infinite weight */
+#define DMS_QUERY_OVERFLOW 4 /* dms_index_query: the query's buckets hold more than 2048 entries */
 
 /* Engines for the sketch and LSH calls (dms_set_option DMS_OPT_ENGINE). */
 #define DMS_ENGINE_FAST 0  /* flattened wave pipeline, work-stealing persistent grid */
@@ -136,6 +137,48 @@ dms_status dms_lsh_keys(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, con
  */
 dms_status dms_jaccard_est(dms_ctx ctx, int64_t n_pairs, const void* a, const void* b, int32_t k,
                            int32_t format, double* out);
+
+/*
+ * Weight-class LSH index for approximate near neighbour search (Section 3):
+ * set s belongs to weight class c = floor(log2 ||x||_1), with ||x||_1 summed
+ * left to right, and is indexed by the (L,K) LSH keys (dms_lsh_keys) of
+ * x * 2^-c, whose ||.||_1 lies in [1, 2) (the scaling is exact).  Indexed rows
+ * must list strictly increasing ids (as uint32) with finite weights >= 0;
+ * other rows get a non-OK status and are left out.  The index keeps the
+ * caller's row_ptr, idx and w (device) for verification: they must stay valid
+ * and unchanged until dms_index_destroy.  The build synchronizes the stream.
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+typedef struct dms_index_s* dms_index;
+dms_status dms_index_build(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                           const double* w, int32_t L, int32_t K, dms_index* out);
+
+/* Per indexed set: its weight class and DMS_SET_* status (device int32[n],
+ * int8[n]; either may be NULL). */
+dms_status dms_index_sets(dms_index ix, int32_t* out_class, int8_t* out_status);
+
+/*
+ * Near neighbours of n_q query sets (CSR, device; rows under the same rules as
+ * indexed rows).  For every class c within span = ceil(log2(1/j1)) + 1 of the
+ * query's own, the query scaled by 2^-c (Jaccard is unchanged when both sets
+ * are scaled alike) is hashed to its L keys; every indexed set of class c
+ * sharing one of them is a candidate; candidates are verified with the exact
+ * weighted Jaccard J = sum min / sum max (both sums in ascending id order).
+ *   out_ids    device int64[n_q*topn]  sets with J >= j1, by J descending then
+ *                                      set ascending; -1 past the last
+ *   out_j      device float64[n_q*topn] their J (0 past the last)
+ *   out_count  device int32[n_q]  results written
+ *   out_candidates device int32[n_q]  distinct candidates verified
+ *   out_status device int8[n_q]   DMS_SET_* of the query, or DMS_QUERY_OVERFLOW
+ *   j1 in (0, 1], topn 1..1024
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_index_query(dms_index ix, int64_t n_q, const int64_t* q_row_ptr, const int32_t* q_idx,
+                           const double* q_w, double j1, int32_t topn, int64_t* out_ids, double* out_j,
+                           int32_t* out_count, int32_t* out_candidates, int8_t* out_status);
+
+/* Free the index (waits for the context's stream). */
+dms_status dms_index_destroy(dms_index ix);
 
 /*
  * Bottom-k sketch (Section 3, bottom-k minhash): DartHash with t = k, phi

@@ -497,7 +497,7 @@ def weight_class(w) -> int:
 def row_ok_for_index(idx, w) -> bool:
     """Index rows must list strictly increasing ids with finite weights >= 0
     and some positive weight, inside the supported range."""
-    idx = np.asarray(idx, dtype=np.int64)
+    idx = np.asarray(idx).astype(np.int64) & 0xFFFFFFFF  # ids are read as uint32
     w = np.asarray(w, dtype=np.float64)
     if len(idx) == 0 or np.any(np.diff(idx) <= 0):
         return False
@@ -509,7 +509,8 @@ def row_ok_for_index(idx, w) -> bool:
 def weighted_jaccard_merge(ia, wa, ib, wb) -> float:
     """J(x, y) = sum min / sum max over the union of the two (id-sorted) rows,
     both sums taken in ascending id order."""
-    ia, ib = np.asarray(ia).tolist(), np.asarray(ib).tolist()
+    ia = (np.asarray(ia).astype(np.int64) & 0xFFFFFFFF).tolist()  # ids are read as uint32
+    ib = (np.asarray(ib).astype(np.int64) & 0xFFFFFFFF).tolist()
     wa, wb = np.asarray(wa, np.float64).tolist(), np.asarray(wb, np.float64).tolist()
     i = j = 0
     smin = smax = 0.0

@@ -34,6 +34,24 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
                                unsigned long long* counter, int blocks, hipStream_t st);
 hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
                                   const uint64_t* sb, int k, double* out, hipStream_t st);
+hipError_t launch_index_prep(int64_t n, const int64_t* rp, const int32_t* idx, const double* w, double* wn,
+                             int32_t* cls, int8_t* status, hipStream_t st);
+size_t index_sort_scratch(int64_t n);
+hipError_t launch_index_order(int64_t n, const int32_t* cls, const int8_t* status, uint64_t* okey,
+                              uint64_t* okey2, int64_t* ord, unsigned long long* n_ok_dev, void* scratch,
+                              size_t scratch_bytes, hipStream_t st);
+hipError_t launch_index_table(int64_t n_ok, const int64_t* ord, const uint64_t* keys, const int32_t* cls, int L,
+                              int l, uint64_t* tmp_k, uint64_t* tmp_v, uint64_t* out_k, uint64_t* out_v,
+                              void* scratch, size_t scratch_bytes, hipStream_t st);
+hipError_t launch_query_prep(int64_t n_q, const int64_t* rp, const int32_t* idx, const double* w, int span,
+                             int64_t* xrp, int32_t* xidx, double* xw, int32_t* qcls, int8_t* qstatus,
+                             hipStream_t st);
+hipError_t launch_index_query(int64_t n_q, int span, int L, const uint64_t* qkeys, const int8_t* xstatus,
+                              const int32_t* qcls, const int8_t* qstatus, const uint64_t* tkeys,
+                              const uint64_t* tvals, int64_t n_ok, const int64_t* q_rp, const int32_t* q_idx,
+                              const double* q_w, const int64_t* d_rp, const int32_t* d_idx, const double* d_w,
+                              double j1, int topn, int64_t* out_ids, double* out_j, int32_t* out_count,
+                              int32_t* out_cand, int8_t* out_status, int n_cu, hipStream_t st);
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                     const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                     uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
@@ -568,3 +586,210 @@ dms_status dms_spec_constants(uint64_t seed, uint32_t t, uint64_t keys[6], uint6
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Weight-class LSH index
+
+struct dms_index_s {
+    dms_ctx ctx = nullptr;
+    int64_t n = 0, n_ok = 0;
+    int L = 0, K = 0;
+    const int64_t* rp = nullptr;  // the caller's sets (read by verification)
+    const int32_t* idx = nullptr;
+    const double* w = nullptr;
+    int32_t* cls = nullptr;       // per set: weight class and status
+    int8_t* status = nullptr;
+    uint64_t* tkeys = nullptr;    // L tables of n_ok sorted (key, value) pairs
+    uint64_t* tvals = nullptr;
+    void* q = nullptr;            // query scratch, grown on demand
+    size_t q_bytes = 0;
+};
+
+namespace {
+
+template <class T>
+hipError_t ix_alloc(T** p, size_t n)
+{
+    *p = nullptr;
+    return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
+}
+
+void ix_free(dms_index ix)
+{
+    (void)hipFree(ix->cls);
+    (void)hipFree(ix->status);
+    (void)hipFree(ix->tkeys);
+    (void)hipFree(ix->tvals);
+    (void)hipFree(ix->q);
+    delete ix;
+}
+
+// ceil(log2(1/j1)) + 1 classes on each side of the query's
+int class_span(double j1) { return (int)std::ceil(std::log2(1.0 / j1)) + 1; }
+
+}  // namespace
+
+dms_status dms_index_build(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                           const double* w, int32_t L, int32_t K, dms_index* out)
+{
+    if (!c || !out) return DMS_EINVAL;
+    c->err.clear();
+    *out = nullptr;
+    if (n_sets < 0 || n_sets >= (int64_t(1) << 31)) return fail(c, DMS_EINVAL, "n_sets outside 0..2^31-1");
+    if (L < 1 || L > 1024 || K < 1 || K > 64 || (int64_t)L * K > 65536)
+        return fail(c, DMS_EINVAL, "L = %d, K = %d out of range", L, K);
+    if (n_sets > 0 && (!row_ptr || !idx || !w)) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    auto* ix = new dms_index_s;
+    ix->ctx = c;
+    ix->n = n_sets;
+    ix->L = L;
+    ix->K = K;
+    ix->rp = row_ptr;
+    ix->idx = idx;
+    ix->w = w;
+    int64_t nnz = 0;
+    hipError_t e = hipSuccess;
+    if (n_sets > 0) {
+        e = hipMemcpyAsync(&nnz, row_ptr + n_sets, sizeof nnz, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    double* wn = nullptr;
+    uint64_t *keys = nullptr, *okey = nullptr, *okey2 = nullptr, *tmp_k = nullptr, *tmp_v = nullptr;
+    int64_t* ord = nullptr;
+    int8_t* kst = nullptr;
+    unsigned long long* n_ok_dev = nullptr;
+    void* scratch = nullptr;
+    const size_t scratch_bytes = dms::index_sort_scratch(n_sets > 0 ? n_sets : 1);
+    if (e == hipSuccess) e = ix_alloc(&ix->cls, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&ix->status, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&wn, (size_t)nnz);
+    if (e == hipSuccess) e = ix_alloc(&keys, (size_t)n_sets * L);
+    if (e == hipSuccess) e = ix_alloc(&kst, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&okey, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&okey2, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&ord, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&tmp_k, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&tmp_v, (size_t)n_sets);
+    if (e == hipSuccess) e = ix_alloc(&n_ok_dev, 1);
+    if (e == hipSuccess) e = hipMalloc(&scratch, scratch_bytes ? scratch_bytes : 1);
+    dms_status rc = DMS_OK;
+    if (e != hipSuccess) rc = fail(c, DMS_ENOMEM, "index allocation: %s", hipGetErrorString(e));
+    if (rc == DMS_OK && n_sets > 0) {
+        // classes and normalised weights, then the (L,K) keys of the normalised sets
+        e = dms::launch_index_prep(n_sets, row_ptr, idx, w, wn, ix->cls, ix->status, st);
+        if (e != hipSuccess) rc = hip_fail(c, e, "index prep");
+        if (rc == DMS_OK) rc = dms_lsh_keys(c, n_sets, row_ptr, idx, wn, L, K, keys, kst);
+        if (rc == DMS_OK) {
+            e = dms::launch_index_order(n_sets, ix->cls, ix->status, okey, okey2, ord, n_ok_dev, scratch,
+                                        scratch_bytes, st);
+            unsigned long long n_ok = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&n_ok, n_ok_dev, sizeof n_ok, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            ix->n_ok = (int64_t)n_ok;
+            if (e != hipSuccess) rc = hip_fail(c, e, "index order");
+        }
+        if (rc == DMS_OK) {
+            e = ix_alloc(&ix->tkeys, (size_t)ix->n_ok * L);
+            if (e == hipSuccess) e = ix_alloc(&ix->tvals, (size_t)ix->n_ok * L);
+            if (e != hipSuccess) rc = fail(c, DMS_ENOMEM, "index tables: %s", hipGetErrorString(e));
+        }
+        for (int l = 0; rc == DMS_OK && l < L; ++l) {
+            e = dms::launch_index_table(ix->n_ok, ord, keys, ix->cls, L, l, tmp_k, tmp_v,
+                                        ix->tkeys + (size_t)l * ix->n_ok, ix->tvals + (size_t)l * ix->n_ok,
+                                        scratch, scratch_bytes, st);
+            if (e != hipSuccess) rc = hip_fail(c, e, "index table");
+        }
+        if (rc == DMS_OK) {
+            e = hipStreamSynchronize(st);  // the temporaries below are freed next
+            if (e != hipSuccess) rc = hip_fail(c, e, "index build");
+        }
+    }
+    (void)hipFree(wn); (void)hipFree(keys); (void)hipFree(kst); (void)hipFree(okey); (void)hipFree(okey2);
+    (void)hipFree(ord); (void)hipFree(tmp_k); (void)hipFree(tmp_v); (void)hipFree(n_ok_dev); (void)hipFree(scratch);
+    if (rc != DMS_OK) {
+        ix_free(ix);
+        return rc;
+    }
+    *out = ix;
+    return DMS_OK;
+}
+
+dms_status dms_index_sets(dms_index ix, int32_t* out_class, int8_t* out_status)
+{
+    if (!ix) return DMS_EINVAL;
+    dms_ctx c = ix->ctx;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = hipSuccess;
+    if (out_class && ix->n)
+        e = hipMemcpyAsync(out_class, ix->cls, (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && out_status && ix->n)
+        e = hipMemcpyAsync(out_status, ix->status, (size_t)ix->n, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "index sets");
+    return DMS_OK;
+}
+
+dms_status dms_index_query(dms_index ix, int64_t n_q, const int64_t* q_row_ptr, const int32_t* q_idx,
+                           const double* q_w, double j1, int32_t topn, int64_t* out_ids, double* out_j,
+                           int32_t* out_count, int32_t* out_candidates, int8_t* out_status)
+{
+    if (!ix) return DMS_EINVAL;
+    dms_ctx c = ix->ctx;
+    c->err.clear();
+    if (n_q < 0 || !(j1 > 0.0 && j1 <= 1.0) || topn < 1 || topn > 1024)
+        return fail(c, DMS_EINVAL, "bad n_q, j1 or topn");
+    if (n_q == 0) return DMS_OK;
+    if (!q_row_ptr || !q_idx || !q_w || !out_ids || !out_j || !out_count || !out_candidates || !out_status)
+        return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    const int span = class_span(j1), span2 = 2 * span + 1;
+    int64_t q_nnz = 0;
+    hipError_t e = hipMemcpyAsync(&q_nnz, q_row_ptr + n_q, sizeof q_nnz, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(c, e, "query size");
+    // scratch: expanded CSR, its keys and statuses, per-query class and status
+    const size_t rows = (size_t)n_q * span2;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_rp = 0, o_idx = o_rp + up((rows + 1) * 8), o_w = o_idx + up((size_t)q_nnz * span2 * 4);
+    const size_t o_keys = o_w + up((size_t)q_nnz * span2 * 8), o_xst = o_keys + up(rows * ix->L * 8);
+    const size_t o_qc = o_xst + up(rows), o_qs = o_qc + up((size_t)n_q * 4), total = o_qs + up((size_t)n_q);
+    if (total > ix->q_bytes) {
+        e = hipStreamSynchronize(st);  // earlier queries may still read the old scratch
+        if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+        (void)hipFree(ix->q);
+        ix->q = nullptr;
+        ix->q_bytes = 0;
+        e = hipMalloc(&ix->q, total);
+        if (e != hipSuccess) return fail(c, DMS_ENOMEM, "query scratch: %s", hipGetErrorString(e));
+        ix->q_bytes = total;
+    }
+    char* b = (char*)ix->q;
+    int64_t* xrp = (int64_t*)(b + o_rp);
+    int32_t* xidx = (int32_t*)(b + o_idx);
+    double* xw = (double*)(b + o_w);
+    uint64_t* qkeys = (uint64_t*)(b + o_keys);
+    int8_t* xst = (int8_t*)(b + o_xst);
+    int32_t* qcls = (int32_t*)(b + o_qc);
+    int8_t* qst = (int8_t*)(b + o_qs);
+    e = dms::launch_query_prep(n_q, q_row_ptr, q_idx, q_w, span, xrp, xidx, xw, qcls, qst, st);
+    if (e != hipSuccess) return hip_fail(c, e, "query prep");
+    dms_status rc = dms_lsh_keys(c, (int64_t)rows, xrp, xidx, xw, ix->L, ix->K, qkeys, xst);
+    if (rc != DMS_OK) return rc;
+    e = dms::launch_index_query(n_q, span, ix->L, qkeys, xst, qcls, qst, ix->tkeys, ix->tvals, ix->n_ok,
+                                q_row_ptr, q_idx, q_w, ix->rp, ix->idx, ix->w, j1, topn, out_ids, out_j,
+                                out_count, out_candidates, out_status, c->n_cu, st);
+    if (e != hipSuccess) return hip_fail(c, e, "query launch");
+    return DMS_OK;
+}
+
+dms_status dms_index_destroy(dms_index ix)
+{
+    if (!ix) return DMS_EINVAL;
+    DeviceGuard g(ix->ctx->device);
+    (void)hipStreamSynchronize(ix->ctx->stream);
+    ix_free(ix);
+    return DMS_OK;
+}

@@ -58,6 +58,6 @@ struct Part {
 };
 
 // Per-set status values written to out_status.
-enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3 };
+enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3, kQueryOverflow = 4 };
 
 }  // namespace dms

@@ -22,7 +22,8 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
            "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
-           "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk"]
+           "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
+           "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -61,6 +62,10 @@ def lib():
         "dms_jaccard_est": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_bbit_pack": ([vp, i64, vp, i32, i32, vp], i32),
         "dms_bottomk": ([vp, i64, vp, vp, vp, i32, vp, vp, vp], i32),
+        "dms_index_build": ([vp, i64, vp, vp, vp, i32, i32, ctypes.POINTER(vp)], i32),
+        "dms_index_sets": ([vp, vp, vp], i32),
+        "dms_index_query": ([vp, i64, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp], i32),
+        "dms_index_destroy": ([vp], i32),
         "dms_jaccard_est_bottomk": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "dms_jaccard_est_bbit": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_unary_map": ([vp, i64, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
@@ -296,6 +301,54 @@ class Context:
         dist = torch.empty((nq, topk), dtype=torch.int32, device=db.device)
         self.dms_hamming_topk(db, db.shape[0], words, queries, nq, topk, ids, dist)
         return ids, dist
+
+
+class LshIndex:
+    """Weight-class (L,K) LSH index over a CSR batch of sets (dms_index_*).
+    The index reads the given device tensors during queries and keeps them."""
+
+    def __init__(self, ctx: Context, row_ptr, idx, w, L: int, K: int):
+        self.ctx, self._keep = ctx, (row_ptr, idx, w)
+        self.n = row_ptr.numel() - 1
+        self._h = ctypes.c_void_p()
+        ctx._stream()
+        ctx._check(lib().dms_index_build(ctx._h, self.n, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
+                                         ctypes.byref(self._h)), "dms_index_build")
+
+    def sets(self):
+        """(class int32 [n], status int8 [n]) of the indexed sets."""
+        torch = self.ctx._torch
+        dev = self._keep[0].device
+        cls = torch.empty(self.n, dtype=torch.int32, device=dev)
+        st = torch.empty(self.n, dtype=torch.int8, device=dev)
+        self.ctx._check(lib().dms_index_sets(self._h, _ptr(cls), _ptr(st)), "dms_index_sets")
+        return cls, st
+
+    def query(self, q_row_ptr, q_idx, q_w, j1: float, topn: int):
+        torch = self.ctx._torch
+        nq = q_row_ptr.numel() - 1
+        dev = q_row_ptr.device
+        out = dict(ids=torch.empty((nq, topn), dtype=torch.int64, device=dev),
+                   j=torch.empty((nq, topn), dtype=torch.float64, device=dev),
+                   count=torch.empty(nq, dtype=torch.int32, device=dev),
+                   candidates=torch.empty(nq, dtype=torch.int32, device=dev),
+                   status=torch.empty(nq, dtype=torch.int8, device=dev))
+        self.ctx._stream()
+        self.ctx._check(lib().dms_index_query(self._h, nq, _ptr(q_row_ptr), _ptr(q_idx), _ptr(q_w), float(j1),
+                                              topn, _ptr(out["ids"]), _ptr(out["j"]), _ptr(out["count"]),
+                                              _ptr(out["candidates"]), _ptr(out["status"])), "dms_index_query")
+        return out
+
+    def close(self):
+        if self._h:
+            lib().dms_index_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:
