@@ -223,6 +223,55 @@ def fingerprint_runs(ctx, torch, out_u32, k, bits=8, steps=5):
     return res
 
 
+def index_run(ctx, torch, n_queries=10_000, j1=0.5, topn=10):
+    """Weight-class LSH index over the (L,K) = (64,8) workload's 1M sets at
+    scales 2^-8..2^8: build time, query throughput for near-duplicate queries
+    (J = 0.9 of a random indexed set, at its own scale), the share whose planted
+    set comes first, and the exact Jaccard of returned pairs re-checked by the
+    oracle on a sample."""
+    from oracle import oracle as O
+    from paper_2005_11547_amd import LshIndex, to_device
+    rp, idx, w = WL.lsh_L64K8()
+    rng = np.random.default_rng(31)
+    n = len(rp) - 1
+    scale = np.repeat(2.0 ** rng.integers(-8, 9, size=n), np.diff(rp))
+    w = w * scale
+    d = to_device(rp, idx, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = LshIndex(ctx, *d, 64, 8)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    picks = rng.choice(n, size=n_queries, replace=False)
+    queries = [WL.near_duplicate(rng, idx[rp[q]:rp[q + 1]], w[rp[q]:rp[q + 1]], J=0.9) for q in picks]
+    qd = to_device(*WL.csr_from_rows(queries))
+    ix.query(*qd, j1, topn)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = ix.query(*qd, j1, topn)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ids, jv = out["ids"].cpu().numpy(), out["j"].cpu().numpy()
+    cand = out["candidates"].cpu().numpy()
+    ok = True
+    for m in range(0, n_queries, n_queries // 50):
+        for r in range(topn):
+            x = int(ids[m, r])
+            if x < 0:
+                break
+            ok &= O.weighted_jaccard_merge(*queries[m], idx[rp[x]:rp[x + 1]], w[rp[x]:rp[x + 1]]) == jv[m, r]
+    res = {"n_sets": n, "L": 64, "K": 8, "j1": j1, "build_s": build_s, "queries": n_queries,
+           "query_ms": ms, "queries_per_s": n_queries / (ms * 1e-3),
+           "planted_top1": float(np.mean(ids[:, 0] == picks)), "mean_candidates": float(cand.mean()),
+           "exact_j_sample": {"queries_checked": 50, "exact": bool(ok)}}
+    log(f"lsh_index: {res}")
+    ix.close()
+    del d, qd
+    return res
+
+
 # The paper's Table 1 (DartMinHash column, mean ms per set on an Intel i7-10510U,
 # one core): (k, ||x||_0, ||x||_1, ms).
 TABLE1 = [(1, 256, 1.0, 0.02), (256, 256, 1.0, 0.17), (4096, 256, 1.0, 2.67), (1, 4096, 1.0, 0.30),
@@ -442,6 +491,7 @@ def main():
         fp = fingerprint_runs(ctx, torch, out_u32, k)
         result["secondary"] = secondary_runs(ctx, torch)
         result["secondary"]["bbit_b8"] = fp
+        result["secondary"]["lsh_index_L64K8"] = index_run(ctx, torch)
     if args.serving_seconds > 0:
         result["serving"] = serving_run(ctx, torch, args.serving_seconds, args.serving_db,
                                         split_nnz=args.serving_split)
