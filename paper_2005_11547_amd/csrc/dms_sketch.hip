@@ -28,19 +28,25 @@ namespace dms {
 
 namespace {
 
-// Every queue is a ring of kCap entries.  A round consumes up to 64 entries
-// and pushes at most 64 into each queue it feeds, and it runs only while every
-// queue it feeds holds at most kTrig entries (consumers take priority above
-// that), so kTrig + 64 <= kCap keeps the rings from overflowing.
-constexpr uint32_t kCap = 96;
-constexpr uint32_t kTrig = kCap - 64;
+// Every queue is a ring.  A round consumes up to 64 entries and pushes at most
+// 64 into each queue it feeds, and it runs only while every queue it feeds
+// holds at most cap - 64 entries (its consumer takes priority above that), so
+// no ring overflows.  The region ring is the smaller one: its rounds are the
+// costliest, and region entries come from few rounds; the dart and pass rings
+// hold two rounds so that their (cheaper) consumers always run 64 lanes wide.
+constexpr uint32_t kCapR = 96;   // region queue (regions with areas left)
+constexpr uint32_t kCapD = 128;  // dart queue (areas with darts left)
+constexpr uint32_t kCapP = 128;  // pass queue (darts with rank <= tau)
+constexpr uint32_t kTrigR = kCapR - 64, kTrigD = kCapD - 64, kTrigP = kCapP - 64;
 
-// Ring slot of a position p < 3 * kCap (head < kCap plus two counts).
-__device__ __forceinline__ uint32_t ring(uint32_t p)
+// Ring slots of positions below 3 * cap (a head below cap plus two counts).
+__device__ __forceinline__ uint32_t ring_r(uint32_t p)
 {
-    p = min(p, p - 2u * kCap);  // unsigned: wraps to a large value when p < 2 * kCap
-    return min(p, p - kCap);
+    p = min(p, p - 2u * kCapR);  // unsigned: wraps to a large value when p < 2 * kCapR
+    return min(p, p - kCapR);
 }
+__device__ __forceinline__ uint32_t ring_d(uint32_t p) { return p & (kCapD - 1); }
+__device__ __forceinline__ uint32_t ring_p(uint32_t p) { return p & (kCapP - 1); }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -99,23 +105,23 @@ __device__ __forceinline__ uint32_t poisson_fast(const uint64_t (&C)[8], const u
 // one base register plus an immediate.
 // Entries name their element by its offset e from the first element of the
 // pass (the weight itself is read back from the CSR only by the accept round).
-constexpr uint32_t kOffRqG = 0;                              // u64[kCap] region hash
-constexpr uint32_t kOffDqA = kOffRqG + 8 * kCap;             // u64[kCap] area hash
-constexpr uint32_t kOffPqA = kOffDqA + 8 * kCap;             // u64[kCap] area hash
-constexpr uint32_t kOffPqRank = kOffPqA + 8 * kCap;          // u64[kCap] rank bits
-constexpr uint32_t kOffRqE = kOffPqRank + 8 * kCap;          // u32[kCap] element offset
-constexpr uint32_t kOffRqRc = kOffRqE + 4 * kCap;            // u32[kCap] rows
-constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCap;           // u32[kCap] areas
-constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCap;        // u32[kCap] areas taken
-constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCap;         // u32[kCap] nu | rho << 10
-constexpr uint32_t kOffDqE = kOffRqM + 4 * kCap;             // u32[kCap]
-constexpr uint32_t kOffDqR = kOffDqE + 4 * kCap;             // u32[kCap]
-constexpr uint32_t kOffDqW = kOffDqR + 4 * kCap;             // u32[kCap]
-constexpr uint32_t kOffDqM = kOffDqW + 4 * kCap;             // u32[kCap] nu|rho<<10|j<<20|X<<25
-constexpr uint32_t kOffPqE = kOffDqM + 4 * kCap;             // u32[kCap]
-constexpr uint32_t kOffPqW = kOffPqE + 4 * kCap;             // u32[kCap]
-constexpr uint32_t kOffPqM = kOffPqW + 4 * kCap;             // u32[kCap] nu|rho<<10|j<<20
-constexpr uint32_t kOffMark = kOffPqM + 4 * kCap;            // i32[64]
+constexpr uint32_t kOffRqG = 0;                              // u64[kCapR] region hash
+constexpr uint32_t kOffDqA = kOffRqG + 8 * kCapR;            // u64[kCapD] area hash
+constexpr uint32_t kOffPqA = kOffDqA + 8 * kCapD;            // u64[kCapP] area hash
+constexpr uint32_t kOffPqRank = kOffPqA + 8 * kCapP;         // u64[kCapP] rank bits
+constexpr uint32_t kOffRqE = kOffPqRank + 8 * kCapP;         // u32[kCapR] element offset
+constexpr uint32_t kOffRqRc = kOffRqE + 4 * kCapR;           // u32[kCapR] rows
+constexpr uint32_t kOffRqNa = kOffRqRc + 4 * kCapR;          // u32[kCapR] areas
+constexpr uint32_t kOffRqFirst = kOffRqNa + 4 * kCapR;       // u32[kCapR] areas taken
+constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | rho << 10
+constexpr uint32_t kOffDqE = kOffRqM + 4 * kCapR;            // u32[kCapD]
+constexpr uint32_t kOffDqR = kOffDqE + 4 * kCapD;            // u32[kCapD]
+constexpr uint32_t kOffDqW = kOffDqR + 4 * kCapD;            // u32[kCapD]
+constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<10|j<<20|X<<25
+constexpr uint32_t kOffPqE = kOffDqM + 4 * kCapD;            // u32[kCapP]
+constexpr uint32_t kOffPqW = kOffPqE + 4 * kCapP;            // u32[kCapP]
+constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<10|j<<20
+constexpr uint32_t kOffMark = kOffPqM + 4 * kCapP;           // i32[64]
 constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits, u64[k] ids
 constexpr uint32_t kQueueBytes = kOffBins;
 constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
@@ -411,7 +417,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     const uint64_t bp = __ballot(pass);
                     const uint64_t bm = __ballot(more);
                     if (pass) {
-                        const uint32_t pos = ring(pq_head + pq_count + rank_in(bp));
+                        const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
                         at<uint64_t>(wb, kOffPqA, pos) = a;
                         at<uint32_t>(wb, kOffPqE, pos) = ei;
                         at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
@@ -419,7 +425,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         at<uint32_t>(wb, kOffPqM, pos) = meta;
                     }
                     if (more) {
-                        const uint32_t pos = ring(dq_head + dq_count + rank_in(bm));
+                        const uint32_t pos = ring_d(dq_head + dq_count + rank_in(bm));
                         at<uint64_t>(wb, kOffDqA, pos) = a;
                         at<uint32_t>(wb, kOffDqE, pos) = ei;
                         at<uint32_t>(wb, kOffDqR, pos) = rv;
@@ -432,11 +438,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 
                 for (;;) {
                     wave_sync();
-                    if (pq_count > kTrig || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
+                    if (pq_count > kTrigP || (pq_count > 0 && dq_count == 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- accept round ----------------
                         const uint32_t m = pq_count < 64 ? pq_count : 64;
                         // lanes past m reread the last entry and stay inactive
-                        const uint32_t pos = ring(pq_head + ((uint32_t)lane < m ? (uint32_t)lane : m - 1));
+                        const uint32_t pos = ring_p(pq_head + ((uint32_t)lane < m ? (uint32_t)lane : m - 1));
                         const uint64_t a = at<uint64_t>(wb, kOffPqA, pos);
                         const double xi = wts[lo + at<uint32_t>(wb, kOffPqE, pos)];
                         const uint32_t wv = at<uint32_t>(wb, kOffPqW, pos);
@@ -468,13 +474,13 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         } else if (acc) {
                             bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
                         }
-                        pq_head = uni(ring(pq_head + m));
+                        pq_head = uni(ring_p(pq_head + m));
                         pq_count = uni(pq_count - m);
-                    } else if (dq_count > kTrig || (dq_count > 0 && rq_count == 0 && !have_chunk)) {
+                    } else if (dq_count > kTrigD || (dq_count > 0 && rq_count == 0 && !have_chunk)) {
                         // ---------------- dart round ----------------
                         const uint32_t m = dq_count < 64 ? dq_count : 64;
                         const bool act = (uint32_t)lane < m;
-                        const uint32_t rpos = ring(dq_head + (act ? (uint32_t)lane : m - 1));
+                        const uint32_t rpos = ring_d(dq_head + (act ? (uint32_t)lane : m - 1));
                         const uint64_t a = at<uint64_t>(wb, kOffDqA, rpos);
                         const uint32_t ei = at<uint32_t>(wb, kOffDqE, rpos);
                         const uint32_t rv = at<uint32_t>(wb, kOffDqR, rpos);
@@ -490,7 +496,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint64_t bm = __ballot(more);
                         wave_sync();  // every entry of the round is read before any write
                         if (pass) {
-                            const uint32_t pos = ring(pq_head + pq_count + rank_in(bp));
+                            const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
                             at<uint64_t>(wb, kOffPqA, pos) = a;
                             at<uint32_t>(wb, kOffPqE, pos) = ei;
                             at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
@@ -499,7 +505,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         }
                         const uint32_t dq_left = dq_count - m;
                         if (more) {
-                            const uint32_t pos = ring(dq_head + m + dq_left + rank_in(bm));
+                            const uint32_t pos = ring_d(dq_head + m + dq_left + rank_in(bm));
                             at<uint64_t>(wb, kOffDqA, pos) = a;
                             at<uint32_t>(wb, kOffDqE, pos) = ei;
                             at<uint32_t>(wb, kOffDqR, pos) = rv;
@@ -507,14 +513,14 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<uint32_t>(wb, kOffDqM, pos) = meta + (1u << 20);
                         }
                         pq_count = uni(pq_count + (uint32_t)__popcll(bp));
-                        dq_head = uni(ring(dq_head + m));
+                        dq_head = uni(ring_d(dq_head + m));
                         dq_count = uni(dq_left + (uint32_t)__popcll(bm));
-                    } else if (rq_pending >= 64 || rq_count > kTrig || (rq_count > 0 && !have_chunk)) {
+                    } else if (rq_pending >= 64 || rq_count > kTrigR || (rq_count > 0 && !have_chunk)) {
                         // ---------------- area round ----------------
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
                         if ((uint32_t)lane < n_items) {
-                            const uint32_t ip = ring(rq_head + lane);
+                            const uint32_t ip = ring_r(rq_head + lane);
                             na = at<uint32_t>(wb, kOffRqNa, ip);
                             first = at<uint32_t>(wb, kOffRqFirst, ip);
                             c = na - first;
@@ -541,7 +547,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         uint64_t a = 0;
                         uint32_t ei = 0;
                         if (act) {
-                            const uint32_t ip = ring(rq_head + (uint32_t)src);
+                            const uint32_t ip = ring_r(rq_head + (uint32_t)src);
                             const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
                             ei = at<uint32_t>(wb, kOffRqE, ip);
                             const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
@@ -564,11 +570,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
                         const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
                         if (last_local + 1 == last_na) {
-                            rq_head = uni(ring(rq_head + last_src + 1));
+                            rq_head = uni(ring_r(rq_head + last_src + 1));
                             rq_count = uni(rq_count - (last_src + 1));
                         } else {
-                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, ring(rq_head + last_src)) = last_local + 1;
-                            rq_head = uni(ring(rq_head + last_src));
+                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, ring_r(rq_head + last_src)) = last_local + 1;
+                            rq_head = uni(ring_r(rq_head + last_src));
                             rq_count = uni(rq_count - last_src);
                         }
                         rq_pending = rq_pending > m ? uni(rq_pending - m) : 0u;
@@ -633,7 +639,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const bool push_r = act && rest > 0;
                         const uint64_t br = __ballot(push_r);
                         if (push_r) {
-                            const uint32_t pos = ring(rq_head + rq_count + rank_in(br));
+                            const uint32_t pos = ring_r(rq_head + rq_count + rank_in(br));
                             at<uint64_t>(wb, kOffRqG, pos) = g;
                             at<uint32_t>(wb, kOffRqE, pos) = e;
                             at<uint32_t>(wb, kOffRqRc, pos) = rcu;
