@@ -365,7 +365,6 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 bool have_chunk = false;
                 uint32_t rq_head = 0, rq_count = 0, dq_head = 0, dq_count = 0;
                 uint32_t pq_head = 0, pq_count = 0;
-                uint32_t rq_pending = 0;   // lower bound of the areas left in the region queue
 
                 auto load_chunk = [&]() {
                     have_chunk = false;
@@ -515,7 +514,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         pq_count = uni(pq_count + (uint32_t)__popcll(bp));
                         dq_head = uni(ring_d(dq_head + m));
                         dq_count = uni(dq_left + (uint32_t)__popcll(bm));
-                    } else if (rq_pending >= 64 || rq_count > kTrigR || (rq_count > 0 && !have_chunk)) {
+                    } else if (rq_count > kTrigR || (rq_count > 0 && !have_chunk)) {
                         // ---------------- area round ----------------
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
@@ -577,7 +576,6 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             rq_head = uni(ring_r(rq_head + last_src));
                             rq_count = uni(rq_count - last_src);
                         }
-                        rq_pending = rq_pending > m ? uni(rq_pending - m) : 0u;
                     } else if (have_chunk) {
                         // ---------------- region round ----------------
                         const uint32_t left = chunk_total - reg_done;
@@ -648,9 +646,6 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<uint32_t>(wb, kOffRqM, pos) = meta;
                         }
                         rq_count = uni(rq_count + (uint32_t)__popcll(br));
-                        // areas added to the region queue, each region counted at most 64 times:
-                        // a lower bound that only steers when area rounds run full
-                        rq_pending = uni(rq_pending + lane63(scan_add(rest < 64 ? rest : 64)));
                         reg_done = uni(reg_done + m);
                         if (wave_any(range)) break;
                         if (reg_done == chunk_total) {
