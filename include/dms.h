@@ -48,7 +48,7 @@ typedef int32_t dms_status;
 /* Options (dms_set_option / dms_get_option).  None changes any output:
  * Theorem 1's output is independent of the phi schedule. */
 #define DMS_OPT_ENGINE 0    /* DMS_ENGINE_* */
-#define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1) */
+#define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1.3) */
 #define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 3) */
 #define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
 #define DMS_OPT_SPLIT_NNZ 4 /* fast engine: sets with more nonzeros are shared by several
@@ -108,6 +108,20 @@ dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
                           const int32_t* idx, const double* w, int32_t k, uint32_t* out_u32,
                           uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                           double* out_rank);
+
+/*
+ * Autotuner for dms_sketch_csr: times the sketch of a prefix of the batch
+ * (its first min(n_sets, 2^26/k) rows, so the rows should be in no particular
+ * order) under candidate schedules -- first phi in {1, 1.15, 1.3, 1.5, 1.8},
+ * then split thresholds in {0, 1024, 4096, 16384} -- and sets DMS_OPT_PHI0 and
+ * DMS_OPT_SPLIT_NNZ on the context to the fastest.  Outputs never depend on
+ * either (Theorem 1's output is independent of the schedule; parts merge
+ * exactly).  Synchronizes the stream; allocates and frees its own buffers.
+ *   out_phi0, out_split: host double* or NULL, receive the chosen values
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
+ */
+dms_status dms_autotune(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                        const double* w, int32_t k, double* out_phi0, double* out_split);
 
 /*
  * (L,K) LSH values (Section 1.2 "Fast similarity search" and Section 3

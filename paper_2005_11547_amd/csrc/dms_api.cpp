@@ -104,7 +104,10 @@ struct dms_ctx_s {
     size_t heavy_bytes = 0;
     uint64_t* partial = nullptr;
     size_t partial_bytes = 0;
-    double phi0 = 1.0;
+    // first phi of the minhash schedule: at 1.3 a second pass is needed with
+    // probability about k^(1-phi) e^(-phi) (0.07 at k = 256), which costs less
+    // than the larger first pass saves (Theorem 1's retry argument)
+    double phi0 = 1.3;
     double lsh_phi0 = 3.0;
     double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
     double phi_max = 1048576.0;
@@ -791,5 +794,75 @@ dms_status dms_index_destroy(dms_index ix)
     DeviceGuard g(ix->ctx->device);
     (void)hipStreamSynchronize(ix->ctx->stream);
     ix_free(ix);
+    return DMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate schedules on a prefix of the caller's batch.
+
+dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx, const double* w,
+                        int32_t k, double* out_phi0, double* out_split)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (n_sets < 1 || k < 1 || k > 4096) return fail(c, DMS_EINVAL, "bad n_sets or k");
+    if (!row_ptr || !idx || !w) return fail(c, DMS_EINVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    // a sample large enough that the last sets to finish weigh little in each trial
+    const int64_t n = n_sets < ((int64_t)1 << 26) / k ? n_sets : ((int64_t)1 << 26) / k;
+    uint32_t* out = nullptr;
+    int8_t* st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc((void**)&out, (size_t)n * k * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&st, (size_t)n);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    dms_status rc = e == hipSuccess ? DMS_OK : fail(c, DMS_ENOMEM, "autotune buffers: %s", hipGetErrorString(e));
+    // best of two timed launches after one warm-up; +inf on failure
+    auto trial = [&](double phi0, double split) -> float {
+        c->phi0 = phi0;
+        c->split_nnz = split;
+        float best = INFINITY;
+        for (int r = 0; r < 3 && rc == DMS_OK; ++r) {
+            hipError_t x = hipEventRecord(e0, c->stream);
+            if (x != hipSuccess) { rc = hip_fail(c, x, "autotune event"); break; }
+            rc = dms_sketch_csr(c, n, row_ptr, idx, w, k, out, nullptr, st, nullptr, nullptr);
+            if (rc != DMS_OK) break;
+            x = hipEventRecord(e1, c->stream);
+            if (x == hipSuccess) x = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+            if (x != hipSuccess) { rc = hip_fail(c, x, "autotune timing"); break; }
+            if (r > 0 && ms < best) best = ms;
+        }
+        return best;
+    };
+    const double keep_phi0 = c->phi0, keep_split = c->split_nnz;
+    double best_phi0 = keep_phi0, best_split = keep_split;
+    if (rc == DMS_OK) {
+        // coordinate search: the first phi, then the split threshold
+        const double phis[] = {1.0, 1.15, 1.3, 1.5, 1.8};
+        float best = INFINITY;
+        for (double p : phis) {
+            const float ms = trial(p, keep_split);
+            if (ms < best) { best = ms; best_phi0 = p; }
+        }
+        const double splits[] = {0.0, 1024.0, 4096.0, 16384.0};
+        best = trial(best_phi0, keep_split);
+        for (double sp : splits) {
+            if (sp == keep_split) continue;
+            const float ms = trial(best_phi0, sp);
+            if (ms < best) { best = ms; best_split = sp; }
+        }
+    }
+    (void)hipFree(out);
+    (void)hipFree(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->phi0 = rc == DMS_OK ? best_phi0 : keep_phi0;
+    c->split_nnz = rc == DMS_OK ? best_split : keep_split;
+    if (rc != DMS_OK) return rc;
+    if (out_phi0) *out_phi0 = best_phi0;
+    if (out_split) *out_split = best_split;
     return DMS_OK;
 }

@@ -23,7 +23,7 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
            "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
-           "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy"]
+           "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -66,6 +66,7 @@ def lib():
         "dms_index_sets": ([vp, vp, vp], i32),
         "dms_index_query": ([vp, i64, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp], i32),
         "dms_index_destroy": ([vp], i32),
+        "dms_autotune": ([vp, i64, vp, vp, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)], i32),
         "dms_jaccard_est_bottomk": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "dms_jaccard_est_bbit": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_unary_map": ([vp, i64, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
@@ -177,6 +178,15 @@ class Context:
         self._stream()
         self._check(lib().dms_jaccard_est(self._h, n_pairs, _ptr(a), _ptr(b), k, fmt, _ptr(out)),
                     "dms_jaccard_est")
+
+    def autotune(self, row_ptr, idx, w, k):
+        """Pick the fastest first phi and split threshold for this batch and k
+        (sets them on the context); returns (phi0, split)."""
+        self._stream()
+        phi0, split = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(lib().dms_autotune(self._h, row_ptr.numel() - 1, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
+                                       ctypes.byref(phi0), ctypes.byref(split)), "dms_autotune")
+        return phi0.value, split.value
 
     def dms_bottomk(self, n_sets, row_ptr, idx, w, k, out_s, out_rank=None, out_status=None):
         self._stream()

@@ -177,3 +177,18 @@ def test_heavy_sets_cut_into_parts(torch, split):
         for k in (1, 100, 256):
             _check_sketch(torch, c, rp2, idx2, w2, k, f"split={split} phi0={phi0} k={k}")
         c.close()
+
+
+def test_autotune_picks_a_candidate_and_changes_no_output(torch):
+    # the tuner times schedules on a prefix of the batch and sets them on the
+    # context; the sketches must stay bit-exact (Theorem 1's output does not
+    # depend on the schedule, and split parts merge exactly)
+    from paper_2005_11547_amd import Context, dms
+    rp, idx, w = WL.batch_k256(seed=61, n_sets=3000)
+    c = Context(SEED)
+    d = _dev(torch, rp, idx, w)
+    phi0, split = c.autotune(*d, 256)
+    assert phi0 in (1.0, 1.15, 1.3, 1.5, 1.8) and split in (0.0, 1024.0, 4096.0, 16384.0)
+    assert c.get_option(dms.OPT_PHI0) == phi0 and c.get_option(dms.OPT_SPLIT_NNZ) == split
+    _check_sketch(torch, c, rp[:401], idx[:rp[400]], w[:rp[400]], 256, f"after autotune phi0={phi0} split={split}")
+    c.close()
