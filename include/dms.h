@@ -49,7 +49,7 @@ typedef int32_t dms_status;
  * Theorem 1's output is independent of the phi schedule. */
 #define DMS_OPT_ENGINE 0    /* DMS_ENGINE_* */
 #define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1.3) */
-#define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 3) */
+#define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 2.5) */
 #define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
 #define DMS_OPT_SPLIT_NNZ 4 /* fast engine: sets with more nonzeros are shared by several
                                wavefronts, one part of at most this many nonzeros each

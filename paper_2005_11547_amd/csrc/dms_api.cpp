@@ -108,7 +108,7 @@ struct dms_ctx_s {
     // probability about k^(1-phi) e^(-phi) (0.07 at k = 256), which costs less
     // than the larger first pass saves (Theorem 1's retry argument)
     double phi0 = 1.3;
-    double lsh_phi0 = 3.0;
+    double lsh_phi0 = 2.5;  // (64,8) LSH: fastest of 2, 2.5, 3, 3.5, 4 on 1M sets
     double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
