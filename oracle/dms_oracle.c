@@ -42,7 +42,11 @@ typedef struct {
     double phi0;               /* first value of phi               */
     int32_t schedule;          /* DMSO_SCHED_*                     */
     double phi_max;            /* give up (status RANGE) beyond this */
+    int32_t hash;              /* DMSO_HASH_*                      */
+    uint64_t tab[8 * 256];     /* tabulation tables (DMSO_HASH_TAB) */
 } dmso_params;
+
+enum { DMSO_HASH_MIX = 0, DMSO_HASH_TAB = 1 };
 
 typedef struct {
     uint32_t i;     /* element id                        */
@@ -70,6 +74,21 @@ static uint64_t mix64(uint64_t z)
 }
 
 uint64_t dmso_mix64(uint64_t z) { return mix64(z); }
+
+/* Simple tabulation hashing (the paper's randomness source, Section 4): the
+ * XOR of one table word per byte of z, tables filled by the Mersenne Twister. */
+static uint64_t tab64(const uint64_t* tab, uint64_t z)
+{
+    uint64_t h = 0;
+    for (int b = 0; b < 8; b++) h ^= tab[b * 256 + ((z >> (8 * b)) & 0xFF)];
+    return h;
+}
+
+/* The hash function of every hashing step of the specification. */
+static uint64_t H(const dmso_params* P, uint64_t z)
+{
+    return P->hash == DMSO_HASH_TAB ? tab64(P->tab, z) : mix64(z);
+}
 
 /* 53 high bits of a hash as a uniform double in [0,1). */
 static double unit53(uint64_t h)
@@ -137,7 +156,7 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
                 double Rr = P->R[rho];
                 double dnu = ldexp(P->u, nu - rho);   /* 2^nu / (t 2^rho) */
                 double drho = ldexp(1.0, rho - nu);   /* 2^rho / 2^nu     */
-                uint64_t g = mix64(P->key_r ^ (((uint64_t)id << 32) |
+                uint64_t g = H(P, P->key_r ^ (((uint64_t)id << 32) |
                                                ((uint64_t)nu << 16) | (uint64_t)rho));
                 cnt->regions++;
                 double wmax = ldexp(1.0, rho); /* w runs over 0 .. 2^rho - 1 */
@@ -149,12 +168,12 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
                         if (tau < Rr + rd * drho) break;
                         if (rd >= 4294967296.0) return DMSO_RANGE;
                         uint32_t w = (uint32_t)wd, r = (uint32_t)rd;
-                        uint64_t a = mix64(g ^ P->key_a ^ (((uint64_t)w << 32) | (uint64_t)r));
+                        uint64_t a = H(P, g ^ P->key_a ^ (((uint64_t)w << 32) | (uint64_t)r));
                         uint32_t X = poisson_count(P, a);
                         cnt->areas++;
                         for (uint32_t j = 0; j < X; j++) {
-                            double U = unit53(mix64(a ^ P->key_u ^ (uint64_t)j));
-                            double V = unit53(mix64(a ^ P->key_v ^ (uint64_t)j));
+                            double U = unit53(H(P, a ^ P->key_u ^ (uint64_t)j));
+                            double V = unit53(H(P, a ^ P->key_v ^ (uint64_t)j));
                             double weight = Wn + (wd + V) * dnu;
                             double rank = Rr + (rd + U) * drho;
                             cnt->generated++;
@@ -164,7 +183,7 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
                                 D.i = id; D.nu = (uint16_t)nu; D.rho = (uint16_t)rho;
                                 D.w = w; D.r = r; D.j = j; D.pad = 0;
                                 D.rank = rank; D.weight = weight;
-                                D.s = mix64(a ^ P->key_s ^ (uint64_t)j);
+                                D.s = H(P, a ^ P->key_s ^ (uint64_t)j);
                                 cnt->accepted++;
                                 if (push_dart(out, &D)) return DMSO_NOMEM;
                             }
@@ -381,8 +400,8 @@ int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const 
     }
     if (st == DMSO_OK) {
         for (int32_t l = 0; l < L; l++) {
-            uint64_t h = mix64(P->key_l ^ (uint64_t)l);
-            for (int32_t m = 0; m < K; m++) h = mix64(h ^ bs[(size_t)l * K + m]);
+            uint64_t h = H(P, P->key_l ^ (uint64_t)l);
+            for (int32_t m = 0; m < K; m++) h = H(P, h ^ bs[(size_t)l * K + m]);
             out_keys[l] = h;
         }
         if (out_s) memcpy(out_s, bs, slots * sizeof(uint64_t));

@@ -38,6 +38,9 @@ NPOIS = 20
 STATUS = {"ok": 0, "empty": 1, "range": 2, "invalid": 3}
 SCHED_PLUS_ONE = 0   # phi = 1, 2, 3, ... (proof of Theorem 1)
 SCHED_DOUBLE = 1     # phi = phi0, 2 phi0, 4 phi0, ...
+HASH_MIX = 0         # SplitMix64 output function keyed by the six keys
+HASH_TAB = 1         # simple tabulation, tables from the Mersenne Twister
+TAB_WORDS = 8 * 256
 MASK64 = (1 << 64) - 1
 
 
@@ -139,6 +142,8 @@ class Params(ctypes.Structure):
         ("phi0", ctypes.c_double),
         ("schedule", ctypes.c_int32),
         ("phi_max", ctypes.c_double),
+        ("hash", ctypes.c_int32),
+        ("tab", ctypes.c_uint64 * TAB_WORDS),
     ]
 
 
@@ -202,9 +207,20 @@ def mix64(z: int) -> int:
     return int(lib().dmso_mix64(z & MASK64))
 
 
+@lru_cache(maxsize=8)
+def tab_tables(seed: int) -> tuple:
+    """Simple-tabulation tables: the MT19937-64 outputs that follow the six
+    keys; table b (for byte b of the hashed word) is outputs 7 + 256 b onwards."""
+    return tuple(mt19937_64(seed, 6 + TAB_WORDS)[6:])
+
+
 def make_params(seed: int, t: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE,
-                phi_max: float = 2.0 ** 20) -> Params:
+                phi_max: float = 2.0 ** 20, hash: int = HASH_MIX) -> Params:
     p = Params()
+    p.hash = hash
+    if hash == HASH_TAB:
+        for i, v in enumerate(tab_tables(seed)):
+            p.tab[i] = v
     for name, v in hash_keys(seed).items():
         setattr(p, name, v)
     for n, c in enumerate(poisson_thresholds()):
@@ -234,10 +250,10 @@ def _csr(row_ptr, idx, w):
 # --------------------------------------------------------------------------
 # Method
 # --------------------------------------------------------------------------
-def darthash(idx, w, tau: float, t: int, seed: int):
+def darthash(idx, w, tau: float, t: int, seed: int, hash: int = HASH_MIX):
     """DartHash_t(x, phi) with tau = phi/||x||_1 given explicitly (Algorithm 1).
     Returns (status, structured array of darts, counters dict)."""
-    P = make_params(seed, t)
+    P = make_params(seed, t, hash=hash)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.float64)
     n = ctypes.c_int64(0)
@@ -251,11 +267,11 @@ def darthash(idx, w, tau: float, t: int, seed: int):
 
 
 def minhash_set(idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
-                schedule: int = SCHED_PLUS_ONE):
+                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
     """DartMinHash of one set (Theorem 1).  Returns (status, s[k] uint64,
     rank[k] float64, phi_final, counters)."""
     t = t_of_k(k) if t is None else t
-    P = make_params(seed, t, phi0, schedule)
+    P = make_params(seed, t, phi0, schedule, hash=hash)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.float64)
     s = np.zeros(k, dtype=np.uint64)
@@ -268,13 +284,13 @@ def minhash_set(idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1
 
 
 def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
-               schedule: int = SCHED_PLUS_ONE, full: bool = False):
+               schedule: int = SCHED_PLUS_ONE, full: bool = False, hash: int = HASH_MIX):
     """DartMinHash of every row of a CSR matrix.
 
     Returns dict with u32 [n,k], bits [n, ceil(k/64)] (uint64), status [n] (int8),
     and with ``full`` also s [n,k], rank [n,k], phi [n], counters [n]."""
     t = t_of_k(k) if t is None else t
-    P = make_params(seed, t, phi0, schedule)
+    P = make_params(seed, t, phi0, schedule, hash=hash)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
     n = len(row_ptr) - 1
     words = (k + 63) // 64
@@ -297,9 +313,9 @@ def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: f
 
 
 def lsh_set(idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
-            schedule: int = SCHED_PLUS_ONE):
+            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
     """(L,K) LSH values of one set.  Returns (status, keys[L], s[L,K], rank[L,K], phi)."""
-    P = make_params(seed, L * K, phi0, schedule)
+    P = make_params(seed, L * K, phi0, schedule, hash=hash)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.float64)
     keys = np.zeros(L, dtype=np.uint64)
@@ -312,8 +328,8 @@ def lsh_set(idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
 
 
 def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
-            schedule: int = SCHED_PLUS_ONE):
-    P = make_params(seed, L * K, phi0, schedule)
+            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
+    P = make_params(seed, L * K, phi0, schedule, hash=hash)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
     n = len(row_ptr) - 1
     keys = np.zeros((n, L), dtype=np.uint64)
@@ -325,10 +341,11 @@ def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
     return dict(keys=keys, status=status)
 
 
-def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE):
+def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE,
+                hash: int = HASH_MIX):
     """Bottom-k sketch of one set (Section 3): the k first darts hitting x, with
     DartHash at t = k.  Returns (status, s[k] uint64, rank[k] float64, phi)."""
-    P = make_params(seed, k, phi0, schedule)
+    P = make_params(seed, k, phi0, schedule, hash=hash)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.float64)
     s = np.zeros(k, dtype=np.uint64)
@@ -340,12 +357,12 @@ def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SC
 
 
 def bottomk_csr(row_ptr, idx, w, k: int, seed: int, phi0: float = 1.0,
-                schedule: int = SCHED_PLUS_ONE):
+                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
     """Bottom-k sketches of every row: dict s [n,k] uint64, rank [n,k] float64,
     u32 [n,k] (low 32 bits of s), status [n] int8."""
     rp, idx, w = _csr(row_ptr, idx, w)
     n = len(rp) - 1
-    P = make_params(seed, k, phi0, schedule)
+    P = make_params(seed, k, phi0, schedule, hash=hash)
     s = np.zeros((n, k), dtype=np.uint64)
     r = np.zeros((n, k), dtype=np.float64)
     st = np.zeros(n, dtype=np.int8)
@@ -535,7 +552,7 @@ def class_span(j1: float) -> int:
     return int(math.ceil(math.log2(1.0 / j1))) + 1
 
 
-def lsh_index_build(row_ptr, idx, w, L: int, K: int, seed: int):
+def lsh_index_build(row_ptr, idx, w, L: int, K: int, seed: int, hash: int = HASH_MIX):
     """The index: per set its class and status, and per table l a dict from
     (class, key of the normalised set) to the ascending ids of the sets there."""
     rp, idx, w = _csr(row_ptr, idx, w)
@@ -555,14 +572,14 @@ def lsh_index_build(row_ptr, idx, w, L: int, K: int, seed: int):
     nrp[1:] = np.cumsum([len(r[0]) for r in rows])
     nidx = np.concatenate([r[0] for r in rows]) if n else np.zeros(0, np.int32)
     nw = np.concatenate([r[1] for r in rows]) if n else np.zeros(0)
-    keys = lsh_csr(nrp, nidx, nw, L, K, seed)["keys"]
+    keys = lsh_csr(nrp, nidx, nw, L, K, seed, hash=hash)["keys"]
     tables = [dict() for _ in range(L)]
     for q in range(n):
         if not ok[q]:
             continue
         for l in range(L):
             tables[l].setdefault((int(cls[q]), int(keys[q, l])), []).append(q)
-    return {"class": cls, "ok": ok, "keys": keys, "tables": tables, "L": L, "K": K, "seed": seed,
+    return {"class": cls, "ok": ok, "keys": keys, "tables": tables, "L": L, "K": K, "seed": seed, "hash": hash,
             "rows": (rp, idx, w)}
 
 
@@ -580,7 +597,7 @@ def lsh_index_query(index, q_idx, q_w, j1: float, topn: int):
     cands = set()
     for c in range(cq - span, cq + span + 1):
         qs = np.ldexp(np.asarray(q_w, np.float64), -c)
-        st, keys, _, _, _ = lsh_set(q_idx, qs, index["L"], index["K"], index["seed"])
+        st, keys, _, _, _ = lsh_set(q_idx, qs, index["L"], index["K"], index["seed"], hash=index["hash"])
         if st != 0:
             continue
         for l in range(index["L"]):

@@ -24,9 +24,9 @@ def mix(z):
     return z ^ (z >> 31)
 
 
-def stream(ids, t, seed, NU, RHO):
+def stream(ids, t, seed, NU, RHO, mix=mix):
     """All darts with element in ids, nu <= NU, rho <= RHO, as a list of
-    dicts sorted by (rank, s)."""
+    dicts sorted by (rank, s); `mix` is the hash function of every step."""
     K = O.hash_keys(seed)
     C = O.poisson_thresholds()
     u = 1.0 / t
