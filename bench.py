@@ -115,20 +115,31 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=25
     return res
 
 
-def secondary_runs(ctx, torch, steps=3):
+def secondary_runs(ctx, torch, steps=3, main=None):
     """Throughput of the other batch workloads (k = 1024 uneven batching,
-    (L,K) = (64,8) LSH keys, and bottom-k sketches with k = 256 of the main
-    batch), each checked bit for bit on a row sample."""
+    (L,K) = (64,8) LSH keys, bottom-k sketches with k = 256 of the main batch,
+    and the main batch under the tabulation-hash variant), each checked bit for
+    bit on a row sample."""
     from oracle import oracle as O
-    from paper_2005_11547_amd import to_device
+    from paper_2005_11547_amd import Context, dms, to_device
     res = {}
     for name, gen, kind in (("uneven_k1024", WL.uneven_k1024, "sketch"),
                             ("lsh_L64K8", WL.lsh_L64K8, "lsh"),
-                            ("bottomk_k256", WL.batch_k256, "bottomk")):
-        rp, idx, w = gen()
+                            ("bottomk_k256", WL.batch_k256, "bottomk"),
+                            ("tabulation_k256", WL.batch_k256, "tabulation")):
+        # the main batch is reused rather than generated again
+        rp, idx, w = main if (main is not None and gen is WL.batch_k256) else gen()
         n = len(rp) - 1
         d = to_device(rp, idx, w)
-        if kind == "sketch":
+        run_ctx = ctx
+        if kind == "tabulation":
+            # the main batch with the tabulation-hash variant of the specification
+            run_ctx = Context(WL.HASH_SEED)
+            run_ctx.set_option(dms.OPT_HASH, dms.HASH_TAB)
+            out = torch.empty((n, 256), dtype=torch.int32, device="cuda")
+            st = torch.empty(n, dtype=torch.int8, device="cuda")
+            run = lambda: run_ctx.dms_sketch_csr(n, d[0], d[1], d[2], 256, out, None, st)
+        elif kind == "sketch":
             out = torch.empty((n, 1024), dtype=torch.int32, device="cuda")
             bits = torch.empty((n, 16), dtype=torch.int64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
@@ -156,7 +167,10 @@ def secondary_runs(ctx, torch, steps=3):
         sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
         sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
         got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
-        if kind == "sketch":
+        if kind == "tabulation":
+            ref = O.sketch_csr(sub_rp, sub_idx, sub_w, 256, WL.HASH_SEED, hash=O.HASH_TAB)["u32"]
+            exact = bool(np.array_equal(got.view(np.uint32), ref))
+        elif kind == "sketch":
             ref = O.sketch_csr(sub_rp, sub_idx, sub_w, 1024, WL.HASH_SEED)["u32"]
             exact = bool(np.array_equal(got.view(np.uint32), ref))
         elif kind == "lsh":
@@ -501,7 +515,7 @@ def main():
         del src, dst
     if args.secondary and args.workload == "batch_k256":
         fp = fingerprint_runs(ctx, torch, out_u32, k)
-        result["secondary"] = secondary_runs(ctx, torch)
+        result["secondary"] = secondary_runs(ctx, torch, main=(rp, idx, w))
         result["secondary"]["bbit_b8"] = fp
         result["secondary"]["lsh_index_L64K8"] = index_run(ctx, torch)
     if args.serving_seconds > 0:

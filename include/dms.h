@@ -45,8 +45,8 @@ typedef int32_t dms_status;
 #define DMS_ENGINE_FAST 0  /* flattened wave pipeline, work-stealing persistent grid */
 #define DMS_ENGINE_PLAIN 1 /* one wave per set, one lane per nonzero, one launch */
 
-/* Options (dms_set_option / dms_get_option).  None changes any output:
- * Theorem 1's output is independent of the phi schedule. */
+/* Options (dms_set_option / dms_get_option).  None but DMS_OPT_HASH changes any
+ * output: Theorem 1's output is independent of the phi schedule. */
 #define DMS_OPT_ENGINE 0    /* DMS_ENGINE_* */
 #define DMS_OPT_PHI0 1      /* first phi of the minhash schedule (default 1.3) */
 #define DMS_OPT_LSH_PHI0 2  /* first phi of the LSH schedule (default 2.5) */
@@ -56,6 +56,15 @@ typedef int32_t dms_status;
                                (default 4096; 0 disables).  The call then reads two counts back
                                from the device before its main launch. */
 #define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
+#define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
+                               Unlike the options above it changes the outputs: sketches made
+                               with different hashes are not comparable. */
+
+/* Hash functions (DMS_OPT_HASH). */
+#define DMS_HASH_MIX 0 /* SplitMix64's output function of (key XOR input) */
+#define DMS_HASH_TAB 1 /* simple tabulation of (key XOR input): XOR of one 64-bit word per input
+                          byte, table b = MT19937-64 outputs 7 + 256 b .. 262 + 256 b for the seed
+                          (the paper's randomness source, Section 4 "Implementation") */
 
 /* Formats of dms_jaccard_est. */
 #define DMS_FMT_U32 0  /* k uint32 minhash values per set */
@@ -371,6 +380,10 @@ const char* dms_status_str(dms_status s);
 dms_status dms_t_of_k(int32_t k, uint32_t* t);
 dms_status dms_spec_constants(uint64_t seed, uint32_t t, uint64_t keys[6], uint64_t pois[20],
                               double* W, double* R, double* u);
+
+/* The 8 x 256 simple-tabulation words of DMS_HASH_TAB for a seed (host array,
+ * table-major).  Errors: DMS_EINVAL (out NULL). */
+dms_status dms_spec_tabulation(uint64_t seed, uint64_t* out);
 
 #ifdef __cplusplus
 }

@@ -16,22 +16,22 @@ namespace dms {
 hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, hipStream_t st);
+                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
 hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                             const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
-                            int8_t* out_status, double phi0, double phi_max, hipStream_t st);
+                            int8_t* out_status, double phi0, double phi_max, int hash, hipStream_t st);
 hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, hipStream_t st);
+                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
 int fast_waves(int mode, int k, int K);
 size_t fast_lds(int mode, int k, int K, int waves);
-const void* fast_kernel_address(int mode);
+const void* fast_kernel_address(int mode, int hash);
 hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,
-                               unsigned long long* counter, int blocks, hipStream_t st);
+                               unsigned long long* counter, int blocks, int hash, hipStream_t st);
 hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
                                   const uint64_t* sb, int k, double* out, hipStream_t st);
 hipError_t launch_index_prep(int64_t n, const int64_t* rp, const int32_t* idx, const double* w, double* wn,
@@ -58,7 +58,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    hipStream_t st);
+                                    int hash, hipStream_t st);
 size_t plan_part_bytes();
 size_t plan_heavy_bytes();
 hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
@@ -69,7 +69,7 @@ hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
-                           unsigned long long* counter, int blocks, hipStream_t st);
+                           unsigned long long* counter, int blocks, int hash, hipStream_t st);
 size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
 int hamming_blocks(int64_t n_db, int n_cu);
 hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
@@ -110,6 +110,7 @@ struct dms_ctx_s {
     double phi0 = 1.3;
     double lsh_phi0 = 2.5;  // (64,8) LSH: fastest of 2, 2.5, 3, 3.5, 4 on 1M sets
     double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
+    int hash = dms::kHashMix;   // DMS_HASH_*
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
     std::string err;
@@ -183,7 +184,7 @@ int resident_blocks(dms_ctx c, int mode, int k, int K)
 {
     const int waves = dms::fast_waves(mode, k, K);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(mode), 64 * waves,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(mode, c->hash), 64 * waves,
                                                      dms::fast_lds(mode, k, K, waves)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -211,6 +212,7 @@ int ctx_device(dms_ctx c) { return c->device; }
 int ctx_n_cu(dms_ctx c) { return c->n_cu; }
 double ctx_phi0(dms_ctx c) { return c->phi0; }
 double ctx_phi_max(dms_ctx c) { return c->phi_max; }
+int ctx_hash(dms_ctx c) { return c->hash; }
 }  // namespace dms
 
 extern "C" {
@@ -269,6 +271,10 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
             return fail(c, DMS_EINVAL, "unknown engine %g", v);
         c->engine = (int)v;
         return DMS_OK;
+    case DMS_OPT_HASH:
+        if (v != DMS_HASH_MIX && v != DMS_HASH_TAB) return fail(c, DMS_EINVAL, "unknown hash %g", v);
+        c->hash = (int)v;
+        return DMS_OK;
     case DMS_OPT_SPLIT_NNZ:
         if (!(v >= 0.0) || v > 1e12 || v != (double)(int64_t)v)
             return fail(c, DMS_EINVAL, "split threshold must be a non-negative integer");
@@ -299,6 +305,7 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_BOTTOMK_PHI0: *v = c->bottomk_phi0; return DMS_OK;
     case DMS_OPT_PHI_MAX: *v = c->phi_max; return DMS_OK;
     case DMS_OPT_SPLIT_NNZ: *v = c->split_nnz; return DMS_OK;
+    case DMS_OPT_HASH: *v = c->hash; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
     }
 }
@@ -322,7 +329,7 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     // beyond 64 KiB the plain engine serves the call
     if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeMinhash, k, 1, 1) > 65536) {
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
-                                     out_status, out_s, out_rank, c->phi0, c->phi_max, c->stream);
+                                     out_status, out_s, out_rank, c->phi0, c->phi_max, c->hash, c->stream);
     } else {
         const int64_t split = (int64_t)c->split_nnz;
         int64_t n_parts = 0;
@@ -350,7 +357,7 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
                                           c->counter, resident_blocks(c, dms::kModeMinhash, k, 1), c->parts,
-                                          n_parts, c->heavy, c->partial, split, c->stream);
+                                          n_parts, c->heavy, c->partial, split, c->hash, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
     return DMS_OK;
@@ -373,7 +380,7 @@ dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const 
     const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 4.0 / std::sqrt((double)k);
     hipError_t e = dms::launch_bottomk_fast(sp, n_sets, row_ptr, idx, w, k, out_s, out_rank, out_status,
                                             phi0, c->phi_max, c->counter,
-                                            resident_blocks(c, dms::kModeBottomK, k, 1), c->stream);
+                                            resident_blocks(c, dms::kModeBottomK, k, 1), c->hash, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bottom-k launch");
     return DMS_OK;
 }
@@ -412,11 +419,11 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     hipError_t e;
     if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeLsh, L, K, 1) > 65536) {
         e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
-                                  c->lsh_phi0, c->phi_max, c->stream);
+                                  c->lsh_phi0, c->phi_max, c->hash, c->stream);
     } else {
         e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
                                  c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::kModeLsh, L, K),
-                                 c->stream);
+                                 c->hash, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");
     return DMS_OK;
@@ -864,5 +871,12 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     if (rc != DMS_OK) return rc;
     if (out_phi0) *out_phi0 = best_phi0;
     if (out_split) *out_split = best_split;
+    return DMS_OK;
+}
+
+dms_status dms_spec_tabulation(uint64_t seed, uint64_t* out)
+{
+    if (!out) return DMS_EINVAL;
+    dms::hash_tables(seed, out);
     return DMS_OK;
 }

@@ -150,11 +150,19 @@ void hash_keys(uint64_t seed, uint64_t keys[6])
     for (int i = 0; i < 6; ++i) keys[i] = gen();
 }
 
+void hash_tables(uint64_t seed, uint64_t tab[kTabWords])
+{
+    std::mt19937_64 gen(seed);
+    for (int i = 0; i < 6; ++i) (void)gen();  // the keys come first
+    for (int i = 0; i < kTabWords; ++i) tab[i] = gen();
+}
+
 bool make_spec(uint64_t seed, uint32_t t, SpecTables* sp)
 {
     std::memset(sp, 0, sizeof *sp);
     uint64_t keys[6];
     hash_keys(seed, keys);
+    hash_tables(seed, sp->tab);
     sp->key_r = keys[0];
     sp->key_a = keys[1];
     sp->key_u = keys[2];

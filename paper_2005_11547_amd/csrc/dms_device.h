@@ -20,6 +20,25 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 }
 
 // The 53 high bits of a hash as a uniform double in [0, 1) (exact conversion).
+// The hash function of the specification, chosen at compile time.
+template <int HK>
+struct Hasher {
+    __device__ explicit Hasher(const SpecTables*) {}
+    __device__ __forceinline__ uint64_t operator()(uint64_t z) const { return mix64(z); }
+};
+template <>
+struct Hasher<kHashTab> {
+    const uint64_t* __restrict__ tab;
+    __device__ explicit Hasher(const SpecTables* sp) : tab(sp->tab) {}
+    __device__ __forceinline__ uint64_t operator()(uint64_t z) const
+    {
+        uint64_t h = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) h ^= tab[b * 256 + ((z >> (8 * b)) & 0xFFu)];
+        return h;
+    }
+};
+
 __device__ __forceinline__ double unit53(uint64_t h)
 {
     return (double)(h >> 11) * 0x1.0p-53;

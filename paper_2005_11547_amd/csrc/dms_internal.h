@@ -9,6 +9,11 @@ namespace dms {
 constexpr int kTable = 64;      // region corners kept in tables (nu, rho < 64)
 constexpr int kMaxIndex = 1024; // nu and rho stay below this in the supported domain
 constexpr int kNumPoisson = 20; // Poisson(1) thresholds for n = 0..19
+constexpr int kTabWords = 8 * 256;  // simple-tabulation tables, one per byte of the hashed word
+
+// The hash of every hashing step: the SplitMix64 output function, or simple
+// tabulation with Mersenne Twister tables (the paper's randomness source).
+enum HashKind : int { kHashMix = 0, kHashTab = 1 };
 
 // Everything a kernel needs to generate darts for one value of t.  Lives in
 // device memory, one copy per t, owned by the context.
@@ -20,11 +25,13 @@ struct SpecTables {
     double u;               // RN(1/t)
     uint32_t t;
     uint32_t pad;
+    uint64_t tab[kTabWords];  // MT19937-64 outputs 7.. for the seed: table b serves byte b
 };
 
 uint32_t t_of_k(int32_t k);
 bool poisson_thresholds(uint64_t out[kNumPoisson]);
 void hash_keys(uint64_t seed, uint64_t keys[6]);
+void hash_tables(uint64_t seed, uint64_t tab[kTabWords]);
 bool make_spec(uint64_t seed, uint32_t t, SpecTables* sp);
 
 // Region corners for any index.  For nu >= 54, RN(2^nu - 1) = 2^nu and

@@ -10,13 +10,14 @@ namespace dms {
 // Walks Algorithm 1 for the elements owned by one lane and hands every accepted
 // dart (rank <= tau, weight <= x_i) to `sink(rank, s)`.  Sets *range when an
 // index leaves the supported domain.
-template <class Sink>
+template <int HK, class Sink>
 __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                                               const int32_t* __restrict__ idx,
                                               const double* __restrict__ w, int64_t b0,
                                               int64_t b1, int lane, double tau, bool* range,
                                               Sink&& sink)
 {
+    const Hasher<HK> H(sp);
     for (int64_t e = b0 + lane; e < b1; e += kWave) {
         const double xi = w[e];
         if (!(xi > 0.0)) continue;
@@ -30,7 +31,7 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                 const double dnu = ldexp(sp->u, nu - rho);
                 const double drho = ldexp(1.0, rho - nu);
                 const uint64_t g =
-                    mix64(sp->key_r ^ ((id << 32) | ((uint64_t)nu << 16) | (uint64_t)rho));
+                    H(sp->key_r ^ ((id << 32) | ((uint64_t)nu << 16) | (uint64_t)rho));
                 for (uint64_t wc = 0;; ++wc) {
                     if (rho < 63 && wc >= (1ull << rho)) break;
                     const double wd = (double)wc;
@@ -41,16 +42,16 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                         const double rd = (double)rc;
                         if (tau < Rr + rd * drho) break;
                         if (rc >= 0x100000000ull) { *range = true; break; }
-                        const uint64_t a = mix64(g ^ sp->key_a ^ ((wc << 32) | rc));
+                        const uint64_t a = H(g ^ sp->key_a ^ ((wc << 32) | rc));
                         const uint32_t X = poisson_count(sp->pois, a);
                         for (uint32_t j = 0; j < X; ++j) {
-                            const double U = unit53(mix64(a ^ sp->key_u ^ (uint64_t)j));
+                            const double U = unit53(H(a ^ sp->key_u ^ (uint64_t)j));
                             const double rank = Rr + (rd + U) * drho;
                             if (!(rank <= tau)) continue;
-                            const double V = unit53(mix64(a ^ sp->key_v ^ (uint64_t)j));
+                            const double V = unit53(H(a ^ sp->key_v ^ (uint64_t)j));
                             const double weight = Wn + (wd + V) * dnu;
                             if (!(weight <= xi)) continue;
-                            sink(rank, mix64(a ^ sp->key_s ^ (uint64_t)j));
+                            sink(rank, H(a ^ sp->key_s ^ (uint64_t)j));
                         }
                     }
                 }
@@ -86,6 +87,7 @@ __device__ __forceinline__ void write_minhash(int64_t set, int k, int lane, int8
 }
 
 // grid: ceil(n_sets / waves) blocks of 64*waves threads; LDS: waves * 16 k bytes.
+template <int HK>
 __global__ void __launch_bounds__(256)
 sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                     const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
@@ -115,7 +117,7 @@ sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
             if (phi > phi_max) { status = kSetRange; break; }
             const double tau = phi / ri.sum;
             bool range = false;
-            lane_darthash(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
+            lane_darthash<HK>(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
                 bucket_min(rank_bits, sval, bucket_of(s, (uint32_t)k),
                            (uint64_t)__double_as_longlong(rank), s);
             });
@@ -164,6 +166,7 @@ __device__ __forceinline__ void lsh_insert(const LshLds& T, int K, uint32_t l, u
 }
 
 // LDS per wave: L*K*16 + L*8 bytes.
+template <int HK>
 __global__ void __launch_bounds__(256)
 lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                  const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
@@ -193,7 +196,7 @@ lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
             if (phi > phi_max) { status = kSetRange; break; }
             const double tau = phi / ri.sum;
             bool range = false;
-            lane_darthash(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
+            lane_darthash<HK>(sp, idx, w, b0, b1, lane, tau, &range, [&](double rank, uint64_t s) {
                 const uint32_t l = bucket_of(s, (uint32_t)L);
                 const uint64_t rb = (uint64_t)__double_as_longlong(rank);
                 // lanes reaching this point together may target the same table:
@@ -217,8 +220,9 @@ lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
     for (int l = lane; l < L; l += kWave) {
         uint64_t h = 0;
         if (status == kSetOk) {
-            h = mix64(sp->key_l ^ (uint64_t)l);
-            for (int m = 0; m < K; ++m) h = mix64(h ^ T.sval[(size_t)l * K + m]);
+            const Hasher<HK> H(sp);
+            h = H(sp->key_l ^ (uint64_t)l);
+            for (int m = 0; m < K; ++m) h = H(h ^ T.sval[(size_t)l * K + m]);
         }
         out_keys[set * L + l] = h;
     }
@@ -238,13 +242,14 @@ int plain_waves_per_block(int k)
 hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, hipStream_t st)
+                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = plain_waves_per_block(k);
     const int64_t blocks = (n_sets + waves - 1) / waves;
     const size_t lds = (size_t)waves * 16 * k;
-    hipLaunchKernelGGL(sketch_plain_kernel, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    auto kern = hash == kHashTab ? sketch_plain_kernel<kHashTab> : sketch_plain_kernel<kHashMix>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s, out_rank,
                        phi0, phi_max);
     return hipGetLastError();
@@ -252,14 +257,15 @@ hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64
 
 hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                             const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
-                            int8_t* out_status, double phi0, double phi_max, hipStream_t st)
+                            int8_t* out_status, double phi0, double phi_max, int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const size_t per_wave = ((size_t)2 * L * K + L) * 8;
     int waves = (int)(65536 / per_wave);
     waves = waves < 1 ? 1 : (waves > 4 ? 4 : waves);
     const int64_t blocks = (n_sets + waves - 1) / waves;
-    hipLaunchKernelGGL(lsh_plain_kernel, dim3((unsigned)blocks), dim3(64 * waves),
+    auto kern = hash == kHashTab ? lsh_plain_kernel<kHashTab> : lsh_plain_kernel<kHashMix>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves),
                        per_wave * waves, st, sp, n_sets, rp, idx, w, L, K, out_keys, out_status,
                        phi0, phi_max);
     return hipGetLastError();

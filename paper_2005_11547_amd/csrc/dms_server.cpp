@@ -29,11 +29,11 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, hipStream_t st);
+                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
 hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, hipStream_t st);
+                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
 size_t fast_lds_bytes(int k, int waves);
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                     const int32_t* idx, const double* w, int k, uint32_t* out_u32,
@@ -41,7 +41,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    hipStream_t st);
+                                    int hash, hipStream_t st);
 hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
                              hipStream_t st);
 size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
@@ -57,6 +57,7 @@ int ctx_device(dms_ctx c);
 int ctx_n_cu(dms_ctx c);
 double ctx_phi0(dms_ctx c);
 double ctx_phi_max(dms_ctx c);
+int ctx_hash(dms_ctx c);
 }  // namespace dms
 
 namespace {
@@ -236,14 +237,14 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
                                                   s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
                                                   dms::ctx_phi_max(S->ctx), s.d_counter + g,
                                                   2 * dms::ctx_n_cu(S->ctx), dp, n_parts, dh, db,
-                                                  n_parts > 0 ? split : 0, st);
+                                                  n_parts > 0 ? split : 0, dms::ctx_hash(S->ctx), st);
             part_base += n_parts;
             part_heavy += n_heavy;
             bucket_base += n_parts * 2 * (int64_t)k;
         } else {
             e = dms::launch_sketch_plain(sp, n, s.d_rp + row0, s.d_idx, s.d_w, k, o32, obits,
                                          s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
-                                         dms::ctx_phi_max(S->ctx), st);
+                                         dms::ctx_phi_max(S->ctx), dms::ctx_hash(S->ctx), st);
         }
         row0 += n;
     }

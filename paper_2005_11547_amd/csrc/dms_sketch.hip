@@ -226,7 +226,7 @@ __device__ __forceinline__ double exact_count(double base, double step, double b
 // buckets keep their minimum), (L,K) LSH (k = L tables keep their K smallest
 // darts) or the bottom-k sketch (a buffer of darts, sorted and cut to the k
 // smallest).  Each wave repeatedly takes the next set index from *next_set.
-template <int MODE>
+template <int MODE, int HK>
 __global__ void __launch_bounds__(256)
 fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __restrict__ rp,
             const int32_t* __restrict__ idx, const double* __restrict__ wts, int k, int K,
@@ -264,6 +264,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     T.K = K;
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
+    const Hasher<HK> H(sp);
     const double u = sp->u;
     const double td = (double)sp->t;
 
@@ -408,7 +409,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     double rank = 0.0;
                     if (has) {
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
-                        const double U = unit53(mix64(a ^ KU));
+                        const double U = unit53(H(a ^ KU));
                         rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                     }
                     const bool pass = has && rank <= tau && rank > tau_prev;
@@ -449,11 +450,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint64_t rb = at<uint64_t>(wb, kOffPqRank, pos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const uint64_t j = (meta >> 20) & 31;
-                        const double V = unit53(mix64(a ^ KV ^ j));
+                        const double V = unit53(H(a ^ KV ^ j));
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         uint64_t s = 0;
-                        if (acc) s = mix64(a ^ KS ^ j);
+                        if (acc) s = H(a ^ KS ^ j);
                         if (LSH) {
                             T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, lane);
                         } else if (BK) {
@@ -487,7 +488,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const uint32_t j = (meta >> 20) & 31, X = meta >> 25;
-                        const double U = unit53(mix64(a ^ KU ^ (uint64_t)j));
+                        const double U = unit53(H(a ^ KU ^ (uint64_t)j));
                         const double rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                         const bool pass = act && rank <= tau && rank > tau_prev;
                         const bool more = act && j + 1 < X;
@@ -560,7 +561,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 wv = local / rc;
                                 rv = local - wv * rc;
                             }
-                            a = mix64(g ^ KA ^ (((uint64_t)wv << 32) | rv));
+                            a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = poisson_fast(C, sPois, a);
                         }
                         emit_area(act, a, ei, rv, wv, meta, X);
@@ -602,7 +603,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rho = local - nu * (uint32_t)B1;
                             }
                             meta = nu | (rho << 10);
-                            g = mix64(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16) | rho));
+                            g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16) | rho));
                             double wc = 1.0, rcn;
                             if (rho == 0) {
                                 // R[0] = 0 and r * 2^-nu is exact: r <= tau * 2^nu
@@ -628,7 +629,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 nau = (uint32_t)nad;
                             }
                             // the region's first area (w = 0, r = 0)
-                            a = mix64(g ^ KA);
+                            a = H(g ^ KA);
                             X = poisson_fast(C, sPois, a);
                             rest = nau - 1;
                         }
@@ -771,8 +772,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             for (int l = lane; l < k; l += kWave) {
                 uint64_t h = 0;
                 if (ok) {
-                    h = mix64(sp->key_l ^ (uint64_t)l);
-                    for (int m2 = 0; m2 < K; ++m2) h = mix64(h ^ T.sval[(size_t)l * K + m2]);
+                    h = H(sp->key_l ^ (uint64_t)l);
+                    for (int m2 = 0; m2 < K; ++m2) h = H(h ^ T.sval[(size_t)l * K + m2]);
                 }
                 out_keys[set * k + l] = h;
             }
@@ -802,15 +803,18 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 // Explicit instantiations: the host launches all three.
-#define DMS_FAST_KERNEL(M)                                                                        \
-    template __global__ void fast_kernel<M>(const SpecTables*, int64_t, const int64_t*, const int32_t*, \
+#define DMS_FAST_KERNEL(M, HK)                                                                    \
+    template __global__ void fast_kernel<M, HK>(const SpecTables*, int64_t, const int64_t*, const int32_t*, \
                                             const double*, int, int, uint32_t*, uint64_t*, int8_t*,     \
                                             uint64_t*, double*, uint64_t*, double, double,             \
                                             unsigned long long*, const Part*, int64_t, HeavySet*,      \
                                             uint64_t*, int64_t);
-DMS_FAST_KERNEL(kModeMinhash)
-DMS_FAST_KERNEL(kModeLsh)
-DMS_FAST_KERNEL(kModeBottomK)
+DMS_FAST_KERNEL(kModeMinhash, kHashMix)
+DMS_FAST_KERNEL(kModeLsh, kHashMix)
+DMS_FAST_KERNEL(kModeBottomK, kHashMix)
+DMS_FAST_KERNEL(kModeMinhash, kHashTab)
+DMS_FAST_KERNEL(kModeLsh, kHashTab)
+DMS_FAST_KERNEL(kModeBottomK, kHashTab)
 #undef DMS_FAST_KERNEL
 
 // Planning.  plan[0] = heavy sets, plan[1] = parts (counting pass); plan[2],
@@ -938,11 +942,15 @@ size_t fast_lds(int mode, int k, int K, int waves)
 int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, 1); }
 size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, 1, waves); }
 
-const void* fast_kernel_address(int mode)
+const void* fast_kernel_address(int mode, int hash)
 {
-    return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh>)
-         : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK>)
-                                : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash>);
+    if (hash == kHashTab)
+        return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh, kHashTab>)
+             : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK, kHashTab>)
+                                    : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash, kHashTab>);
+    return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh, kHashMix>)
+         : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK, kHashMix>)
+                                : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash, kHashMix>);
 }
 
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
@@ -951,7 +959,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    hipStream_t st)
+                                    int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeMinhash, k, 1);
@@ -959,7 +967,8 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_parts + n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<kModeMinhash>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    auto kern = hash == kHashTab ? fast_kernel<kModeMinhash, kHashTab> : fast_kernel<kModeMinhash, kHashMix>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
                        (HeavySet*)heavy, partial, split);
@@ -970,17 +979,17 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, hipStream_t st)
+                              unsigned long long* counter, int blocks, int hash, hipStream_t st)
 {
     return launch_sketch_fast_split(sp, n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s,
                                     out_rank, phi0, phi_max, counter, blocks, nullptr, 0, nullptr,
-                                    nullptr, 0, st);
+                                    nullptr, 0, hash, st);
 }
 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
-                           unsigned long long* counter, int blocks, hipStream_t st)
+                           unsigned long long* counter, int blocks, int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeLsh, L, K);
@@ -988,7 +997,8 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<kModeLsh>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    auto kern = hash == kHashTab ? fast_kernel<kModeLsh, kHashTab> : fast_kernel<kModeLsh, kHashMix>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
                        (const Part*)nullptr, (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr,
@@ -999,7 +1009,7 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
 hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,
-                               unsigned long long* counter, int blocks, hipStream_t st)
+                               unsigned long long* counter, int blocks, int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeBottomK, k, 1);
@@ -1007,7 +1017,8 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    hipLaunchKernelGGL(fast_kernel<kModeBottomK>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
+    auto kern = hash == kHashTab ? fast_kernel<kModeBottomK, kHashTab> : fast_kernel<kModeBottomK, kHashMix>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        out_s, out_rank, (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)nullptr,
                        (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0);

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libdms.so")
 DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
 SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
-OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0 = 0, 1, 2, 3, 4, 5
+OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH = 0, 1, 2, 3, 4, 5, 6
+HASH_MIX, HASH_TAB = 0, 1
 FMT_U32, FMT_1BIT = 0, 1
 
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
@@ -23,7 +24,8 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
            "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
-           "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune"]
+           "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune",
+           "dms_spec_tabulation"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -66,6 +68,7 @@ def lib():
         "dms_index_sets": ([vp, vp, vp], i32),
         "dms_index_query": ([vp, i64, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp], i32),
         "dms_index_destroy": ([vp], i32),
+        "dms_spec_tabulation": ([u64, vp], i32),
         "dms_autotune": ([vp, i64, vp, vp, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)], i32),
         "dms_jaccard_est_bottomk": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "dms_jaccard_est_bbit": ([vp, i64, vp, vp, i32, i32, vp], i32),
@@ -118,6 +121,16 @@ def spec_constants(seed: int, t: int) -> dict:
     if st != DMS_OK:
         raise DMSError(f"dms_spec_constants -> {st}")
     return dict(keys=keys, pois=pois, W=W, R=R, u=u.value)
+
+
+def spec_tabulation(seed: int):
+    """The library's simple-tabulation tables for the seed (host only)."""
+    import numpy as np
+    out = np.zeros(8 * 256, np.uint64)
+    st = lib().dms_spec_tabulation(seed, _ptr(out))
+    if st != DMS_OK:
+        raise DMSError(f"dms_spec_tabulation -> {st}")
+    return out
 
 
 class Context:

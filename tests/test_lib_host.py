@@ -41,6 +41,12 @@ def test_library_constants_equal_oracle_constants():
             assert lib["u"] == u
 
 
+def test_library_tabulation_tables_equal_oracle():
+    # std::mt19937_64 in the library against the oracle's own MT19937-64
+    for seed in (0, 2005_11547, 2 ** 64 - 1):
+        assert [int(v) for v in P.spec_tabulation(seed)] == list(O.tab_tables(seed))
+
+
 def test_library_t_of_k_equals_oracle():
     for k in list(range(1, 4097)) + [8192, 65536]:
         assert P.t_of_k(k) == O.t_of_k(k), k
