@@ -195,6 +195,7 @@ struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
     {
+        (void)hipGetLastError();  // a launch below reports its own error, not an earlier one
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         if (prev != dev) (void)hipSetDevice(dev);
     }

@@ -177,6 +177,7 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
     s.n_q = (int64_t)s.query_row.size();
     const int64_t rows = (int64_t)order.size();
     hipStream_t st = s.stream;
+    (void)hipGetLastError();  // the launches below report their own errors only
     hipError_t e = hipMemcpyAsync(s.d_rp, s.h_rp, (rows + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz)
         e = hipMemcpyAsync(s.d_idx, s.h_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice, st);

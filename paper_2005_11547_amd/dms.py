@@ -138,8 +138,10 @@ class Context:
 
     def __init__(self, seed: int, device: int = 0, engine: int | None = None):
         import torch
+        import weakref
         self.device = device
         self._h = ctypes.c_void_p()
+        self._dependents = weakref.WeakSet()  # servers and indexes built on this context
         self._check(lib().dms_create(ctypes.byref(self._h), device, seed), "dms_create")
         self.seed = seed
         if engine is not None:
@@ -152,7 +154,11 @@ class Context:
             raise DMSError(f"{what}: {lib().dms_status_str(st).decode()} {msg}")
 
     def close(self):
+        """Destroy the context, and first every server and index built on it
+        (the C ABI requires them to go before their context)."""
         if self._h:
+            for dep in list(self._dependents):
+                dep.close()
             lib().dms_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -337,6 +343,7 @@ class LshIndex:
         ctx._stream()
         ctx._check(lib().dms_index_build(ctx._h, self.n, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
                                          ctypes.byref(self._h)), "dms_index_build")
+        ctx._dependents.add(self)
 
     def sets(self):
         """(class int32 [n], status int8 [n]) of the indexed sets."""
@@ -388,6 +395,7 @@ class Server:
                                      ctypes.byref(self._h))
         if st != DMS_OK:
             raise DMSError(f"dms_server_create: {lib().dms_status_str(st).decode()}")
+        ctx._dependents.add(self)
         self._np = np
 
     def close(self):

@@ -74,7 +74,8 @@ def served(torch, ctx):
     arrival, kind, k, rp, idx, w = _trace(rng, 240, 20_000.0)
     srv = Server(ctx, db, topk=10, max_batch=64, max_inflight=3)
     out = srv.replay(arrival, kind, k, rp, idx, w)
-    return dict(db_bits=db_bits, db=db, trace=(arrival, kind, k, rp, idx, w), out=out, srv=srv)
+    yield dict(db_bits=db_bits, db=db, trace=(arrival, kind, k, rp, idx, w), out=out, srv=srv)
+    srv.close()  # a server goes before its context
 
 
 def test_served_results_equal_oracle(served):
@@ -149,3 +150,18 @@ def test_split_threshold_does_not_change_results(torch, ctx, served, split):
         assert np.array_equal(got["sketch"][r], served["out"]["sketch"][r]), (split, r)
         assert got["status"][r] == served["out"]["status"][r]
         assert np.array_equal(got["ids"][r], served["out"]["ids"][r])
+
+
+def test_closing_a_context_closes_its_server_and_index_first(torch, ctx, served):
+    # the C ABI needs servers and indexes destroyed before their context; the
+    # binding does it, and no stale HIP error reaches later calls
+    from paper_2005_11547_amd import Context, LshIndex, Server, to_device
+    c2 = Context(SEED)
+    srv = Server(c2, served["db"], topk=10, max_batch=8, max_inflight=1)
+    rp, idx, w = WL.csr_from_rows([([1, 5, 9], [1.0, 2.0, 0.5]), ([2, 3], [1.0, 1.0])])
+    ix = LshIndex(c2, *to_device(rp, idx, w), 4, 2)
+    c2.close()
+    assert not srv._h and not ix._h
+    out = ctx.sketch(*to_device(rp, idx, w), 64)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["u32"].cpu().numpy().view(np.uint32), O.sketch_csr(rp, idx, w, 64, SEED)["u32"])
