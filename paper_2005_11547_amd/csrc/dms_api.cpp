@@ -26,6 +26,7 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               double* out_rank, double phi0, double phi_max,
                               unsigned long long* counter, int blocks, int hash, hipStream_t st);
 int fast_waves(int mode, int k, int K);
+int fast_blocks_per_cu(int mode, int k, int K, int waves);
 size_t fast_lds(int mode, int k, int K, int waves);
 const void* fast_kernel_address(int mode, int hash);
 hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
@@ -185,9 +186,12 @@ int resident_blocks(dms_ctx c, int mode, int k, int K)
     const int waves = dms::fast_waves(mode, k, K);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(mode, c->hash), 64 * waves,
-                                                     dms::fast_lds(mode, k, K, waves)) != hipSuccess ||
-        per_cu < 1)
+                                                     dms::fast_lds(mode, k, K, waves)) != hipSuccess)
         per_cu = 1;
+    // the query ignores the LDS allocation granule; take the smaller count
+    const int by_lds = dms::fast_blocks_per_cu(mode, k, K, waves);
+    if (by_lds < per_cu) per_cu = by_lds;
+    if (per_cu < 1) per_cu = 1;
     return per_cu * c->n_cu;
 }
 

@@ -6,15 +6,17 @@
 // that run 64 lanes wide, connected by small queues in LDS:
 //
 //   region round : expands elements into their (nu, rho) regions, hashes the
-//                  region (g) and its first area (a), draws that area's
-//                  Poisson(1) dart count and its first dart's rank; regions
-//                  with more areas go to the region queue, passing darts to
-//                  the pass queue, areas with more darts to the dart queue.
+//                  region (g) and its first area (a), tells from a whether the
+//                  area holds no dart, one, or more, and draws its first
+//                  dart's rank; regions with more areas go to the region queue,
+//                  passing darts to the pass queue, areas with more darts to
+//                  the dart queue.
 //   area round   : expands queued regions into their remaining areas, hashes
-//                  them, draws their dart counts and first ranks (as above).
+//                  them and draws their first ranks (as above).
 //   dart round   : draws the rank uniform of the next dart of each queued
-//                  area; darts with rank <= tau go to the pass queue; an area
-//                  with more darts goes back to the dart queue.
+//                  area (and the area's exact Poisson(1) count); darts with
+//                  rank <= tau go to the pass queue; an area with more darts
+//                  goes back to the dart queue.
 //   accept round : draws the weight uniform; darts with weight <= x_i get their
 //                  id hash and enter the bucket minima.
 //
@@ -34,7 +36,9 @@ namespace {
 // no ring overflows.  The region ring is the smaller one: its rounds are the
 // costliest, and region entries come from few rounds; the dart and pass rings
 // hold two rounds so that their (cheaper) consumers always run 64 lanes wide.
-constexpr uint32_t kCapR = 96;   // region queue (regions with areas left)
+// With these sizes three waves of k = 256 fit 40,960 bytes, so twelve waves
+// share a CU.
+constexpr uint32_t kCapR = 80;   // region queue (regions with areas left)
 constexpr uint32_t kCapD = 128;  // dart queue (areas with darts left)
 constexpr uint32_t kCapP = 128;  // pass queue (darts with rank <= tau)
 constexpr uint32_t kTrigR = kCapR - 64, kTrigD = kCapD - 64, kTrigP = kCapP - 64;
@@ -98,6 +102,13 @@ __device__ __forceinline__ uint32_t poisson_fast(const uint64_t (&C)[8], const u
         while (x < (uint32_t)kNumPoisson && a >= pois[x]) ++x;
     }
     return x;
+}
+
+// min(X, 2) for the Poisson(1) count X of an area hash: enough to tell an
+// empty area, a one-dart area and an area with more darts apart.
+__device__ __forceinline__ uint32_t poisson_head(const uint64_t (&C)[8], uint64_t a)
+{
+    return (uint32_t)(a >= C[0]) + (uint32_t)(a >= C[1]);
 }
 
 // LDS of one wave: queues at fixed offsets from the wave's base, then the k
@@ -237,6 +248,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 {
     constexpr bool LSH = MODE == kModeLsh;
     constexpr bool BK = MODE == kModeBottomK;
+    // Region and area rounds only need to know whether an area holds one dart
+    // or more than one; with kLazyX the exact Poisson count is drawn (from the
+    // same area hash) by the dart round, which sees only areas with two or more
+    // darts.  Measured faster for minhash and bottom-k, slower for LSH keys.
+    constexpr bool kLazyX = !LSH;
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
     double* sR = sW + kTable;
@@ -430,7 +446,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         at<uint32_t>(wb, kOffDqE, pos) = ei;
                         at<uint32_t>(wb, kOffDqR, pos) = rv;
                         at<uint32_t>(wb, kOffDqW, pos) = wv;
-                        at<uint32_t>(wb, kOffDqM, pos) = meta | (X << 25) | (1u << 20);
+                        at<uint32_t>(wb, kOffDqM, pos) = meta | (kLazyX ? 0u : X << 25) | (1u << 20);
                     }
                     pq_count = uni(pq_count + (uint32_t)__popcll(bp));
                     dq_count = uni(dq_count + (uint32_t)__popcll(bm));
@@ -487,7 +503,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t wv = at<uint32_t>(wb, kOffDqW, rpos);
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
-                        const uint32_t j = (meta >> 20) & 31, X = meta >> 25;
+                        const uint32_t j = (meta >> 20) & 31;
+                        const uint32_t X = kLazyX ? poisson_fast(C, sPois, a) : meta >> 25;
                         const double U = unit53(H(a ^ KU ^ (uint64_t)j));
                         const double rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                         const bool pass = act && rank <= tau && rank > tau_prev;
@@ -562,7 +579,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rv = local - wv * rc;
                             }
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                            X = poisson_fast(C, sPois, a);
+                            X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
                         }
                         emit_area(act, a, ei, rv, wv, meta, X);
                         // advance the region queue by m areas
@@ -630,7 +647,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             }
                             // the region's first area (w = 0, r = 0)
                             a = H(g ^ KA);
-                            X = poisson_fast(C, sPois, a);
+                            X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
                             rest = nau - 1;
                         }
                         const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
@@ -917,26 +934,35 @@ hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, 
 // Waves per block: the count (1..4, at most 64 KiB of LDS per block) that
 // keeps the most waves resident in a CU's 160 KiB of LDS; ties go to the
 // larger block, which shares one copy of the tables.
+size_t fast_lds(int mode, int k, int K, int waves)
+{
+    return kTablesBytes + (size_t)waves * wave_lds_bytes(mode, k, K);
+}
+
+// A CU has 160 KiB of LDS and hands it to blocks in units of 1,280 bytes (measured
+// on gfx950: a block of 14,880 bytes occupies 15,360, so ten such blocks fit, not
+// eleven; the runtime's occupancy query does not round and over-counts).
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kLdsGranule = 1280;
+
+int fast_blocks_per_cu(int mode, int k, int K, int waves)
+{
+    const size_t block = fast_lds(mode, k, K, waves);
+    const size_t held = (block + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+    return block > 65536 ? 0 : (int)(kLdsPerCu / held);
+}
+
 int fast_waves(int mode, int k, int K)
 {
-    constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t per = wave_lds_bytes(mode, k, K);
     int best = 1, best_resident = 0;
     for (int w = 1; w <= 4; ++w) {
-        const size_t block = kTablesBytes + (size_t)w * per;
-        if (block > 65536) break;
-        const int resident = w * (int)(kLdsPerCu / block);
+        const int resident = w * fast_blocks_per_cu(mode, k, K, w);
         if (resident >= best_resident) {
             best = w;
             best_resident = resident;
         }
     }
     return best;
-}
-
-size_t fast_lds(int mode, int k, int K, int waves)
-{
-    return kTablesBytes + (size_t)waves * wave_lds_bytes(mode, k, K);
 }
 
 int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, 1); }
