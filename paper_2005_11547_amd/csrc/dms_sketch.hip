@@ -419,14 +419,19 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // Called by all 64 lanes; the `act` lanes carry an area.  Region
                 // and area rounds run only while both queues hold fewer than 64
                 // entries, so neither can overflow.
+                // `corner` marks a region's first area in rank row 0 (rho = 0,
+                // r = 0): its rank R[0] + (0 + U) 2^-nu is U 2^-nu exactly (R[0] = 0,
+                // and scaling by a power of two is exact while ranks stay normal,
+                // as they do for every weight in the supported domain).
                 auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
-                                     uint32_t meta, uint32_t X) {
+                                     uint32_t meta, uint32_t X, bool corner) {
                     const bool has = act && X > 0;
                     double rank = 0.0;
                     if (has) {
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const double U = unit53(H(a ^ KU));
-                        rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
+                        rank = corner ? ldexp(U, -nu)
+                                      : r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                     }
                     const bool pass = has && rank <= tau && rank > tau_prev;
                     const bool more = has && X > 1;
@@ -581,7 +586,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
                         }
-                        emit_area(act, a, ei, rv, wv, meta, X);
+                        emit_area(act, a, ei, rv, wv, meta, X, false);
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
                         const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
@@ -604,54 +609,73 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<int32_t>(wb, kOffMark, nreg_excl > reg_done ? nreg_excl - reg_done : 0) = lane;
                         wave_sync();
                         const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
-                        const double x = __shfl(ex, src, kWave);
                         const uint32_t id = (uint32_t)__shfl(eid, src, kWave);
                         const uint32_t s_excl = (uint32_t)__shfl(nreg_excl, src, kWave);
                         const bool act = (uint32_t)lane < m;
+                        const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
                         uint32_t X = 0, rest = 0, meta = 0, rcu = 1, nau = 1;
                         uint64_t a = 0, g = 0;
-                        if (act) {
-                            const uint32_t local = reg_done + (uint32_t)lane - s_excl;
-                            uint32_t nu = local, rho = 0;
-                            if (B1 > 1) {
-                                nu = (uint32_t)((float)local * inv_b1);
+                        if (B1 == 1) {
+                            // tau < R[1] = 1: every region lies in rank row 0 and has one
+                            // column; its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact)
+                            if (act) {
+                                const uint32_t nu = reg_done + (uint32_t)lane - s_excl;
+                                meta = nu;
+                                g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
+                                const double rcn = fmin(floor(ldexp(tau, (int)nu)) + 1.0, ldexp(1.0, (int)nu));
+                                if (rcn >= 2147483648.0) {
+                                    range = true;
+                                } else {
+                                    rcu = (uint32_t)rcn;
+                                    nau = rcu;
+                                }
+                                a = H(g ^ KA);
+                                X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
+                                rest = nau - 1;
+                            }
+                            emit_area(act, a, e, 0u, 0u, meta, X, true);
+                        } else {
+                            const double x = __shfl(ex, src, kWave);
+                            if (act) {
+                                // region `local` of the element: nu = local / B1, rho = local % B1
+                                const uint32_t local = reg_done + (uint32_t)lane - s_excl;
+                                uint32_t nu = (uint32_t)((float)local * inv_b1);
                                 while (nu * (uint32_t)B1 > local) --nu;
                                 while ((nu + 1) * (uint32_t)B1 <= local) ++nu;
-                                rho = local - nu * (uint32_t)B1;
+                                const uint32_t rho = local - nu * (uint32_t)B1;
+                                meta = nu | (rho << 10);
+                                g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16) | rho));
+                                double wc = 1.0, rcn;
+                                if (rho == 0) {
+                                    // R[0] = 0 and r * 2^-nu is exact: r <= tau * 2^nu
+                                    const double rcap = ldexp(1.0, (int)nu);
+                                    rcn = floor(ldexp(tau, (int)nu)) + 1.0;
+                                    rcn = rcn < rcap ? rcn : rcap;
+                                } else {
+                                    const double Wn = w_corner(sW, u, (int)nu), Rr = r_corner(sR, (int)rho);
+                                    const double dnu = ldexp(u, (int)nu - (int)rho);
+                                    const double drho = ldexp(1.0, (int)rho - (int)nu);
+                                    const double wcap = ldexp(1.0, (int)rho);
+                                    wc = exact_count(Wn, dnu, x, wcap,
+                                                     floor((x - Wn) * td * ldexp(1.0, (int)rho - (int)nu)) + 1.0);
+                                    const double rcap = ldexp(1.0, (int)nu);
+                                    rcn = exact_count(Rr, drho, tau, rcap,
+                                                      floor((tau - Rr) * ldexp(1.0, (int)nu - (int)rho)) + 1.0);
+                                }
+                                const double nad = wc * rcn;
+                                if (wc > 4294967296.0 || rcn > 4294967296.0 || nad >= 2147483648.0) {
+                                    range = true;
+                                } else {
+                                    rcu = (uint32_t)rcn;
+                                    nau = (uint32_t)nad;
+                                }
+                                // the region's first area (w = 0, r = 0)
+                                a = H(g ^ KA);
+                                X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
+                                rest = nau - 1;
                             }
-                            meta = nu | (rho << 10);
-                            g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16) | rho));
-                            double wc = 1.0, rcn;
-                            if (rho == 0) {
-                                // R[0] = 0 and r * 2^-nu is exact: r <= tau * 2^nu
-                                const double rcap = ldexp(1.0, (int)nu);
-                                rcn = floor(ldexp(tau, (int)nu)) + 1.0;
-                                rcn = rcn < rcap ? rcn : rcap;
-                            } else {
-                                const double Wn = w_corner(sW, u, (int)nu), Rr = r_corner(sR, (int)rho);
-                                const double dnu = ldexp(u, (int)nu - (int)rho);
-                                const double drho = ldexp(1.0, (int)rho - (int)nu);
-                                const double wcap = ldexp(1.0, (int)rho);
-                                wc = exact_count(Wn, dnu, x, wcap,
-                                                 floor((x - Wn) * td * ldexp(1.0, (int)rho - (int)nu)) + 1.0);
-                                const double rcap = ldexp(1.0, (int)nu);
-                                rcn = exact_count(Rr, drho, tau, rcap,
-                                                  floor((tau - Rr) * ldexp(1.0, (int)nu - (int)rho)) + 1.0);
-                            }
-                            const double nad = wc * rcn;
-                            if (wc > 4294967296.0 || rcn > 4294967296.0 || nad >= 2147483648.0) {
-                                range = true;
-                            } else {
-                                rcu = (uint32_t)rcn;
-                                nau = (uint32_t)nad;
-                            }
-                            // the region's first area (w = 0, r = 0)
-                            a = H(g ^ KA);
-                            X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
-                            rest = nau - 1;
+                            emit_area(act, a, e, 0u, 0u, meta, X, false);
                         }
-                        const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
-                        emit_area(act, a, e, 0u, 0u, meta, X);
                         const bool push_r = act && rest > 0;
                         const uint64_t br = __ballot(push_r);
                         if (push_r) {
