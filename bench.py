@@ -187,11 +187,13 @@ def secondary_runs(ctx, torch, steps=3, main=None):
     return res
 
 
-def fingerprint_runs(ctx, torch, out_u32, k, bits=8, steps=5):
-    """b-bit fingerprints of the main batch's minhashes: pack, the b-bit
-    estimate over row pairs (2i, 2i+1), and the unary map.  All three are HBM
-    bound: GB/s of their algorithmic bytes against the 8 TB/s peak, each checked
-    bit for bit on a row sample."""
+def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5):
+    """Estimates and fingerprints of the main batch's sketches: the u32 and
+    1-bit estimates over row pairs (2i, 2i+1), b-bit packing, the b-bit
+    estimate over the same pairs, and the unary map.  All are HBM bound: GB/s
+    of their algorithmic bytes against the 8 TB/s peak, each checked bit for
+    bit on a row sample."""
+    from paper_2005_11547_amd import dms
     from oracle import oracle as O
     n = out_u32.shape[0]
     words = (k * bits + 63) // 64
@@ -201,13 +203,22 @@ def fingerprint_runs(ctx, torch, out_u32, k, bits=8, steps=5):
     uidx = torch.empty((n, k), dtype=torch.int32, device="cuda")
     pa, pb = packed[0:2 * n_pairs:2], packed[1:2 * n_pairs:2]
     ea, eb = pa.contiguous(), pb.contiguous()
+    ua_all, ub_all = out_u32[0:2 * n_pairs:2].contiguous(), out_u32[1:2 * n_pairs:2].contiguous()
+    ba_all, bb_all = out_bits[0:2 * n_pairs:2].contiguous(), out_bits[1:2 * n_pairs:2].contiguous()
+    est_u32 = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
+    est_1bit = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
+    bwords = (k + 63) // 64
     runs = {
+        "estimate_u32": (lambda: ctx.dms_jaccard_est(n_pairs, ua_all, ub_all, k, dms.FMT_U32, est_u32),
+                         n_pairs * (8.0 * k + 8.0)),
+        "estimate_1bit": (lambda: ctx.dms_jaccard_est(n_pairs, ba_all, bb_all, k, dms.FMT_1BIT, est_1bit),
+                          n_pairs * (16.0 * bwords + 8.0)),
         "pack": (lambda: ctx.dms_bbit_pack(n, out_u32, k, bits, packed), n * (4.0 * k + 8.0 * words)),
         "estimate": (lambda: ctx.dms_jaccard_est_bbit(n_pairs, ea, eb, k, bits, est),
                      n_pairs * (16.0 * words + 8.0)),
         "unary_map": (lambda: ctx.dms_unary_map(n, out_u32, k, bits, uidx), n * 8.0 * k),
     }
-    res = {"bits": bits, "n_sets": n, "k": k}
+    res = {"bits": bits, "n_sets": n, "k": k, "pairs": "rows (2i, 2i + 1)"}
     for name, (fn, nbytes) in runs.items():
         fn()
         torch.cuda.synchronize()
@@ -231,9 +242,14 @@ def fingerprint_runs(ctx, torch, out_u32, k, bits=8, steps=5):
     ok &= np.array_equal(est[torch.from_numpy(rows).cuda()].cpu().numpy(),
                          O.jaccard_est_bbit(ref_pa, O.bbit_pack(ub, bits), k, bits))
     ok &= np.array_equal(uidx[ra].cpu().numpy(), O.unary_map(ua, bits)[0])
+    sel = torch.from_numpy(rows).cuda()
+    ok &= np.array_equal(est_u32[sel].cpu().numpy(), O.jaccard_est_u32(ua, ub))
+    wa = out_bits[ra].cpu().numpy().view(np.uint64)
+    wb = out_bits[ra + 1].cpu().numpy().view(np.uint64)
+    ok &= np.array_equal(est_1bit[sel].cpu().numpy(), O.jaccard_est_1bit(wa, wb, k))
     res["bit_exact_sample"] = {"rows_checked": int(len(rows)), "exact": bool(ok)}
     log(f"fingerprints: {res}")
-    del packed, est, uidx, ea, eb
+    del packed, est, uidx, ea, eb, ua_all, ub_all, ba_all, bb_all, est_u32, est_1bit
     return res
 
 
@@ -517,7 +533,7 @@ def main():
         log(f"stream copy of {nb} bytes: {result['roofline']['hbm_copy_gbs']:.0f} GB/s (read+write)")
         del src, dst
     if args.secondary and args.workload == "batch_k256":
-        fp = fingerprint_runs(ctx, torch, out_u32, k)
+        fp = fingerprint_runs(ctx, torch, out_u32, out_bits, k)
         result["secondary"] = secondary_runs(ctx, torch, main=(rp, idx, w))
         result["secondary"]["bbit_b8"] = fp
         result["secondary"]["lsh_index_L64K8"] = index_run(ctx, torch)

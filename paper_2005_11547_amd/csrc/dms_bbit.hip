@@ -10,8 +10,64 @@
 
 namespace dms {
 
+hipError_t launch_bbit_jaccard_vec(int64_t n_pairs, const uint64_t* a, const uint64_t* b, int k, int bits,
+                                   double* out, hipStream_t st, bool* done);
+
 namespace {
 constexpr int kPackWaves = 4;  // waves per block of the pack kernel
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+}
+
+// Rows that are whole words (k * b divisible by 64, k divisible by 4) with b a
+// power of two: the input is one stream of 16-byte vectors (four minhashes,
+// 4b fingerprint bits) and the output one stream of words, G = 16 / b vectors
+// per word.  Each lane packs its vector, the G lanes of a word OR their parts
+// together by butterflies, and the first writes the word (b = 32: each vector
+// is two words).
+__global__ void __launch_bounds__(256)
+bbit_pack_vec_kernel(int64_t n_vecs, const uint4* __restrict__ v, int b, int g_log,
+                     uint64_t* __restrict__ out)
+{
+    const uint32_t mask = b == 32 ? 0xffffffffu : (1u << b) - 1u;
+    const int G = 1 << g_log;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of 64: groups stay whole
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_vecs; q += stride) {
+        const uint4 x = v[q];
+        if (b == 32) {
+            reinterpret_cast<uint4*>(out)[q] = x;  // two words: minhash 2i low, 2i + 1 high
+            continue;
+        }
+        uint64_t part = (uint64_t)(x.x & mask) | ((uint64_t)(x.y & mask) << b) |
+                        ((uint64_t)(x.z & mask) << (2 * b)) | ((uint64_t)(x.w & mask) << (3 * b));
+        const int r = (int)(q & (G - 1));
+        part <<= 4 * b * r;
+        for (int o = G >> 1; o > 0; o >>= 1) part |= (uint64_t)__shfl_xor((long long)part, o, kWave);
+        if (r == 0) out[q >> g_log] = part;
+    }
+}
+
+// Unary map over 16-byte vectors (k divisible by 4): the column j of the
+// vector's first minhash advances by a fixed step per grid-stride iteration.
+__global__ void __launch_bounds__(256)
+unary_map_vec_kernel(int64_t n_vecs, const uint4* __restrict__ v, int k, int b, uint4* __restrict__ out)
+{
+    const uint32_t mask = (uint32_t)((1ull << b) - 1ull);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t j = (uint32_t)((4 * q) % k);
+    const uint32_t step = (uint32_t)((4 * stride) % k);
+    for (; q < n_vecs; q += stride) {
+        const uint4 x = v[q];
+        uint4 y;
+        y.x = (j << b) + (x.x & mask);
+        y.y = ((j + 1) << b) + (x.y & mask);
+        y.z = ((j + 2) << b) + (x.z & mask);
+        y.w = ((j + 3) << b) + (x.w & mask);
+        out[q] = y;
+        j += step;
+        if (j >= (uint32_t)k) j -= (uint32_t)k;
+    }
 }
 
 // One wave per (row, chunk of 64 fingerprints).  The chunk's 64 * b bits are
@@ -115,6 +171,15 @@ hipError_t launch_bbit_pack(int64_t n_sets, const uint32_t* v, int k, int b, uin
                             hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
+    if ((b & (b - 1)) == 0 && k % 4 == 0 && ((int64_t)k * b) % 64 == 0 && aligned16(v) && aligned16(out)) {
+        const int64_t n_vecs = n_sets * (int64_t)(k / 4);
+        const int g_log = b == 32 ? 0 : (b == 16 ? 0 : b == 8 ? 1 : b == 4 ? 2 : b == 2 ? 3 : 4);
+        int64_t blocks = (n_vecs + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(bbit_pack_vec_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_vecs,
+                           (const uint4*)v, b, g_log, out);
+        return hipGetLastError();
+    }
     const int words = (int)(((int64_t)k * b + 63) / 64);
     const int chunks = (k + 63) / 64;
     int64_t blocks = (n_sets * chunks + kPackWaves - 1) / kPackWaves;
@@ -128,6 +193,9 @@ hipError_t launch_bbit_jaccard(int64_t n_pairs, const uint64_t* a, const uint64_
                                double* out, hipStream_t st)
 {
     if (n_pairs <= 0) return hipSuccess;
+    bool done = false;
+    hipError_t e = launch_bbit_jaccard_vec(n_pairs, a, b_, k, b, out, st, &done);
+    if (done || e != hipSuccess) return e;
     const int words = (int)(((int64_t)k * b + 63) / 64);
     int64_t blocks = (n_pairs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
@@ -140,6 +208,14 @@ hipError_t launch_unary_map(int64_t n_sets, const uint32_t* v, int k, int b, int
                             hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
+    if (k % 4 == 0 && aligned16(v) && aligned16(out)) {
+        const int64_t n_vecs = n_sets * (int64_t)(k / 4);
+        int64_t blocks = (n_vecs + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(unary_map_vec_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_vecs,
+                           (const uint4*)v, k, b, (uint4*)out);
+        return hipGetLastError();
+    }
     int64_t blocks = n_sets < 65536 ? n_sets : 65536;
     hipLaunchKernelGGL(unary_map_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_sets, v, k, b, out);
     return hipGetLastError();
