@@ -219,18 +219,23 @@ def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5):
         "unary_map": (lambda: ctx.dms_unary_map(n, out_u32, k, bits, uidx), n * 8.0 * k),
     }
     res = {"bits": bits, "n_sets": n, "k": k, "pairs": "rows (2i, 2i + 1)"}
+    # each timed call starts after 512 MiB of unrelated writes, so its inputs come
+    # from HBM, not from the 256 MB last-level cache
+    flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.int64, device="cuda")
     for name, (fn, nbytes) in runs.items():
         fn()
         torch.cuda.synchronize()
         if name == "pack":  # the estimate reads the packed rows
             ea.copy_(packed[0:2 * n_pairs:2]); eb.copy_(packed[1:2 * n_pairs:2])
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
+        ms = 0.0
+        for rep in range(steps):
+            flush.fill_(rep)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1) / steps
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = {"ms": ms, "gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
     rows = np.linspace(0, n_pairs - 1, 200).astype(np.int64)
@@ -249,7 +254,7 @@ def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5):
     ok &= np.array_equal(est_1bit[sel].cpu().numpy(), O.jaccard_est_1bit(wa, wb, k))
     res["bit_exact_sample"] = {"rows_checked": int(len(rows)), "exact": bool(ok)}
     log(f"fingerprints: {res}")
-    del packed, est, uidx, ea, eb, ua_all, ub_all, ba_all, bb_all, est_u32, est_1bit
+    del packed, est, uidx, ea, eb, ua_all, ub_all, ba_all, bb_all, est_u32, est_1bit, flush
     return res
 
 

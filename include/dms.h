@@ -120,7 +120,7 @@ dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
 
 /*
  * Autotuner for dms_sketch_csr: times the sketch of a prefix of the batch
- * (its first min(n_sets, 2^26/k) rows, so the rows should be in no particular
+ * (its first min(n_sets, 2^28/k) rows, so the rows should be in no particular
  * order) under candidate schedules -- first phi in {1, 1.15, 1.3, 1.5, 1.8},
  * then split thresholds in {0, 1024, 4096, 16384} -- and sets DMS_OPT_PHI0 and
  * DMS_OPT_SPLIT_NNZ on the context to the fastest.  Outputs never depend on

@@ -820,8 +820,9 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     if (n_sets < 1 || k < 1 || k > 4096) return fail(c, DMS_EINVAL, "bad n_sets or k");
     if (!row_ptr || !idx || !w) return fail(c, DMS_EINVAL, "NULL pointer");
     DeviceGuard g(c->device);
-    // a sample large enough that the last sets to finish weigh little in each trial
-    const int64_t n = n_sets < ((int64_t)1 << 26) / k ? n_sets : ((int64_t)1 << 26) / k;
+    // a sample large enough that the last sets to finish weigh little in each
+    // trial (shorter prefixes favour a large first phi, which trims the tail)
+    const int64_t n = n_sets < ((int64_t)1 << 28) / k ? n_sets : ((int64_t)1 << 28) / k;
     uint32_t* out = nullptr;
     int8_t* st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
