@@ -147,12 +147,21 @@ __host__ __device__ constexpr uint32_t bk_cap(int k)
     return c;
 }
 
+// LSH table bookkeeping after the L sorted lists: one count byte per table
+// (K <= 64), padded to 8 bytes, then -- only past 64 tables -- the owner slots
+// of the insertion election; up to 64 tables borrow the expansion marks, which
+// are never live during an accept round.
+__host__ __device__ constexpr size_t lsh_aux_bytes(int L)
+{
+    return (size_t)((L + 7) / 8) * 8 + (L > 64 ? (size_t)4 * L : 0);
+}
+
 // Bytes of the result area after the queues: k bucket minima (minhash), L
-// sorted lists of K darts plus counts and owner slots (LSH), or the dart
-// buffer (bottom-k).
+// sorted lists of K darts plus their bookkeeping (LSH), or the dart buffer
+// (bottom-k).
 __host__ __device__ constexpr size_t sink_bytes(int mode, int k, int K)
 {
-    return mode == kModeLsh ? (size_t)16 * k * K + (size_t)8 * k
+    return mode == kModeLsh ? (size_t)16 * k * K + lsh_aux_bytes(k)
          : mode == kModeBottomK ? (size_t)16 * bk_cap(k)
                                 : (size_t)16 * k;
 }
@@ -166,7 +175,7 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
 struct LshTables {
     uint64_t* rank;
     uint64_t* sval;
-    int32_t* cnt;
+    uint8_t* cnt;
     int32_t* owner;
     int K;
 
@@ -275,8 +284,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     LshTables T;
     T.rank = bin_rank;
     T.sval = bin_s;
-    T.cnt = reinterpret_cast<int32_t*>(bin_s + k * K);
-    T.owner = T.cnt + k;
+    T.cnt = reinterpret_cast<uint8_t*>(bin_s + k * K);
+    T.owner = k <= kWave ? &at<int32_t>(wb, kOffMark, 0)
+                         : reinterpret_cast<int32_t*>(T.cnt + ((k + 7) / 8) * 8);
     T.K = K;
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
