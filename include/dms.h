@@ -57,8 +57,12 @@ typedef int32_t dms_status;
                                from the device before its main launch. */
 #define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
 #define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
-                               Unlike the options above it changes the outputs: sketches made
+                               Unlike the other options it changes the outputs: sketches made
                                with different hashes are not comparable. */
+#define DMS_OPT_ORDER 7     /* fast engine: 1 (default) hands sets to wavefronts largest first
+                               (by a log-scale class of the nonzero count, a stable sort on the
+                               device before the main launch), 0 in input order.  Batches of
+                               2^31 sets or more always run in input order. */
 
 /* Hash functions (DMS_OPT_HASH). */
 #define DMS_HASH_MIX 0 /* SplitMix64's output function of (key XOR input) */

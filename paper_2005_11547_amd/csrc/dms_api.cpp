@@ -11,82 +11,8 @@
 
 #include "../../include/dms.h"
 #include "dms_internal.h"
+#include "dms_launch.h"
 
-namespace dms {
-hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
-hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
-                            int8_t* out_status, double phi0, double phi_max, int hash, hipStream_t st);
-hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                              const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                              uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                              double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
-int fast_waves(int mode, int k, int K);
-int fast_blocks_per_cu(int mode, int k, int K, int waves);
-size_t fast_lds(int mode, int k, int K, int waves);
-const void* fast_kernel_address(int mode, int hash);
-hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                               const int32_t* idx, const double* w, int k, uint64_t* out_s,
-                               double* out_rank, int8_t* out_status, double phi0, double phi_max,
-                               unsigned long long* counter, int blocks, int hash, hipStream_t st);
-hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
-                                  const uint64_t* sb, int k, double* out, hipStream_t st);
-hipError_t launch_index_prep(int64_t n, const int64_t* rp, const int32_t* idx, const double* w, double* wn,
-                             int32_t* cls, int8_t* status, hipStream_t st);
-size_t index_sort_scratch(int64_t n);
-hipError_t launch_index_order(int64_t n, const int32_t* cls, const int8_t* status, uint64_t* okey,
-                              uint64_t* okey2, int64_t* ord, unsigned long long* n_ok_dev, void* scratch,
-                              size_t scratch_bytes, hipStream_t st);
-hipError_t launch_index_table(int64_t n_ok, const int64_t* ord, const uint64_t* keys, const int32_t* cls, int L,
-                              int l, uint64_t* tmp_k, uint64_t* tmp_v, uint64_t* out_k, uint64_t* out_v,
-                              void* scratch, size_t scratch_bytes, hipStream_t st);
-hipError_t launch_query_prep(int64_t n_q, const int64_t* rp, const int32_t* idx, const double* w, int span,
-                             int64_t* xrp, int32_t* xidx, double* xw, int32_t* qcls, int8_t* qstatus,
-                             hipStream_t st);
-hipError_t launch_index_query(int64_t n_q, int span, int L, const uint64_t* qkeys, const int8_t* xstatus,
-                              const int32_t* qcls, const int8_t* qstatus, const uint64_t* tkeys,
-                              const uint64_t* tvals, int64_t n_ok, const int64_t* q_rp, const int32_t* q_idx,
-                              const double* q_w, const int64_t* d_rp, const int32_t* d_idx, const double* d_w,
-                              double j1, int topn, int64_t* out_ids, double* out_j, int32_t* out_count,
-                              int32_t* out_cand, int8_t* out_status, int n_cu, hipStream_t st);
-hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                                    double* out_rank, double phi0, double phi_max,
-                                    unsigned long long* counter, int blocks, const void* parts,
-                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    int hash, hipStream_t st);
-size_t plan_part_bytes();
-size_t plan_heavy_bytes();
-hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
-                             unsigned long long* plan, hipStream_t st);
-hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
-                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
-                            hipStream_t st);
-hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                           const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
-                           int8_t* out_status, double phi0, double phi_max,
-                           unsigned long long* counter, int blocks, int hash, hipStream_t st);
-size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
-int hamming_blocks(int64_t n_db, int n_cu);
-hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
-                          int64_t n_q, int topk, int64_t* out_ids, int32_t* out_dist,
-                          uint64_t* partial, int n_blocks, hipStream_t st);
-hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks,
-                     hipStream_t st);
-hipError_t launch_bbit_pack(int64_t n_sets, const uint32_t* v, int k, int b, uint64_t* out,
-                            hipStream_t st);
-hipError_t launch_bbit_jaccard(int64_t n_pairs, const uint64_t* a, const uint64_t* b_, int k, int b,
-                               double* out, hipStream_t st);
-hipError_t launch_unary_map(int64_t n_sets, const uint32_t* v, int k, int b, int32_t* out,
-                            hipStream_t st);
-hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
-                          double* out, hipStream_t st);
-}  // namespace dms
 
 struct dms_ctx_s {
     int device = 0;
@@ -112,6 +38,9 @@ struct dms_ctx_s {
     double lsh_phi0 = 2.5;  // (64,8) LSH: fastest of 2, 2.5, 3, 3.5, 4 on 1M sets
     double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
     int hash = dms::kHashMix;   // DMS_HASH_*
+    int order = 1;              // DMS_OPT_ORDER: largest sets first
+    void* order_buf = nullptr;  // its keys, values and sort scratch
+    size_t order_bytes = 0;
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
     std::string err;
@@ -195,6 +124,26 @@ int resident_blocks(dms_ctx c, int mode, int k, int K)
     return per_cu * c->n_cu;
 }
 
+// Largest-first order of the batch for the fast engine's cursor (DMS_OPT_ORDER),
+// or nullptr for input order.
+dms_status size_order(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const uint32_t** order)
+{
+    *order = nullptr;
+    if (!c->order || n_sets < 2 || n_sets >= ((int64_t)1 << 31)) return DMS_OK;
+    const size_t need = dms::size_order_bytes(n_sets);
+    if (need > c->order_bytes) {
+        if (c->order_buf) (void)hipFree(c->order_buf);
+        c->order_buf = nullptr;
+        c->order_bytes = 0;
+        hipError_t e = hipMalloc(&c->order_buf, need);
+        if (e != hipSuccess) return fail(c, DMS_ENOMEM, "hipMalloc(%zu bytes of order scratch): %s", need, hipGetErrorString(e));
+        c->order_bytes = need;
+    }
+    hipError_t e = dms::launch_size_order(n_sets, row_ptr, c->order_buf, c->order_bytes, order, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "size order");
+    return DMS_OK;
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -256,6 +205,7 @@ dms_status dms_destroy(dms_ctx c)
     if (c->parts) (void)hipFree(c->parts);
     if (c->heavy) (void)hipFree(c->heavy);
     if (c->partial) (void)hipFree(c->partial);
+    if (c->order_buf) (void)hipFree(c->order_buf);
     delete c;
     return DMS_OK;
 }
@@ -279,6 +229,10 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
     case DMS_OPT_HASH:
         if (v != DMS_HASH_MIX && v != DMS_HASH_TAB) return fail(c, DMS_EINVAL, "unknown hash %g", v);
         c->hash = (int)v;
+        return DMS_OK;
+    case DMS_OPT_ORDER:
+        if (v != 0.0 && v != 1.0) return fail(c, DMS_EINVAL, "order must be 0 or 1");
+        c->order = (int)v;
         return DMS_OK;
     case DMS_OPT_SPLIT_NNZ:
         if (!(v >= 0.0) || v > 1e12 || v != (double)(int64_t)v)
@@ -311,6 +265,7 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_PHI_MAX: *v = c->phi_max; return DMS_OK;
     case DMS_OPT_SPLIT_NNZ: *v = c->split_nnz; return DMS_OK;
     case DMS_OPT_HASH: *v = c->hash; return DMS_OK;
+    case DMS_OPT_ORDER: *v = c->order; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
     }
 }
@@ -359,10 +314,12 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
                 if (e != hipSuccess) return hip_fail(c, e, "sketch planning");
             }
         }
+        const uint32_t* order = nullptr;
+        if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
                                           c->counter, resident_blocks(c, dms::kModeMinhash, k, 1), c->parts,
-                                          n_parts, c->heavy, c->partial, split, c->hash, c->stream);
+                                          n_parts, c->heavy, c->partial, split, order, c->hash, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
     return DMS_OK;
@@ -383,9 +340,12 @@ dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const 
     if (st != DMS_OK) return st;
     // phi0 = 1 + 4/sqrt(k) finds k darts in the first pass but for a 4-sigma shortfall
     const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 4.0 / std::sqrt((double)k);
+    const uint32_t* order = nullptr;
+    if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
     hipError_t e = dms::launch_bottomk_fast(sp, n_sets, row_ptr, idx, w, k, out_s, out_rank, out_status,
                                             phi0, c->phi_max, c->counter,
-                                            resident_blocks(c, dms::kModeBottomK, k, 1), c->hash, c->stream);
+                                            resident_blocks(c, dms::kModeBottomK, k, 1), order, c->hash,
+                                            c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bottom-k launch");
     return DMS_OK;
 }
@@ -426,9 +386,11 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
                                   c->lsh_phi0, c->phi_max, c->hash, c->stream);
     } else {
+        const uint32_t* order = nullptr;
+        if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
         e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
                                  c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::kModeLsh, L, K),
-                                 c->hash, c->stream);
+                                 order, c->hash, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");
     return DMS_OK;

@@ -1,0 +1,104 @@
+// Host-side launchers of the library's kernels (defined in the .hip files)
+// and the few context accessors the serving loop uses (defined in dms_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dms.h"
+#include "dms_internal.h"
+
+namespace dms {
+hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
+hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                            int8_t* out_status, double phi0, double phi_max, int hash, hipStream_t st);
+hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                              const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                              uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                              double* out_rank, double phi0, double phi_max,
+                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
+int fast_waves(int mode, int k, int K);
+int fast_blocks_per_cu(int mode, int k, int K, int waves);
+size_t fast_lds(int mode, int k, int K, int waves);
+const void* fast_kernel_address(int mode, int hash);
+hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                               const int32_t* idx, const double* w, int k, uint64_t* out_s,
+                               double* out_rank, int8_t* out_status, double phi0, double phi_max,
+                               unsigned long long* counter, int blocks, const uint32_t* order, int hash,
+                               hipStream_t st);
+hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
+                                  const uint64_t* sb, int k, double* out, hipStream_t st);
+hipError_t launch_index_prep(int64_t n, const int64_t* rp, const int32_t* idx, const double* w, double* wn,
+                             int32_t* cls, int8_t* status, hipStream_t st);
+size_t index_sort_scratch(int64_t n);
+hipError_t launch_index_order(int64_t n, const int32_t* cls, const int8_t* status, uint64_t* okey,
+                              uint64_t* okey2, int64_t* ord, unsigned long long* n_ok_dev, void* scratch,
+                              size_t scratch_bytes, hipStream_t st);
+hipError_t launch_index_table(int64_t n_ok, const int64_t* ord, const uint64_t* keys, const int32_t* cls, int L,
+                              int l, uint64_t* tmp_k, uint64_t* tmp_v, uint64_t* out_k, uint64_t* out_v,
+                              void* scratch, size_t scratch_bytes, hipStream_t st);
+hipError_t launch_query_prep(int64_t n_q, const int64_t* rp, const int32_t* idx, const double* w, int span,
+                             int64_t* xrp, int32_t* xidx, double* xw, int32_t* qcls, int8_t* qstatus,
+                             hipStream_t st);
+hipError_t launch_index_query(int64_t n_q, int span, int L, const uint64_t* qkeys, const int8_t* xstatus,
+                              const int32_t* qcls, const int8_t* qstatus, const uint64_t* tkeys,
+                              const uint64_t* tvals, int64_t n_ok, const int64_t* q_rp, const int32_t* q_idx,
+                              const double* q_w, const int64_t* d_rp, const int32_t* d_idx, const double* d_w,
+                              double j1, int topn, int64_t* out_ids, double* out_j, int32_t* out_count,
+                              int32_t* out_cand, int8_t* out_status, int n_cu, hipStream_t st);
+hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
+                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
+                                    double* out_rank, double phi0, double phi_max,
+                                    unsigned long long* counter, int blocks, const void* parts,
+                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
+                                    const uint32_t* order, int hash, hipStream_t st);
+size_t plan_part_bytes();
+size_t plan_heavy_bytes();
+hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
+                             unsigned long long* plan, hipStream_t st);
+hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
+                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
+                            hipStream_t st);
+hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
+                           const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
+                           int8_t* out_status, double phi0, double phi_max,
+                           unsigned long long* counter, int blocks, const uint32_t* order, int hash,
+                           hipStream_t st);
+size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
+int hamming_blocks(int64_t n_db, int n_cu);
+hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
+                          int64_t n_q, int topk, int64_t* out_ids, int32_t* out_dist,
+                          uint64_t* partial, int n_blocks, hipStream_t st);
+hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks,
+                     hipStream_t st);
+hipError_t launch_bbit_pack(int64_t n_sets, const uint32_t* v, int k, int b, uint64_t* out,
+                            hipStream_t st);
+hipError_t launch_bbit_jaccard(int64_t n_pairs, const uint64_t* a, const uint64_t* b_, int k, int b,
+                               double* out, hipStream_t st);
+hipError_t launch_unary_map(int64_t n_sets, const uint32_t* v, int k, int b, int32_t* out,
+                            hipStream_t st);
+hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
+                          double* out, hipStream_t st);
+size_t fast_lds_bytes(int k, int waves);
+hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
+                             hipStream_t st);
+size_t size_order_bytes(int64_t n_sets);
+hipError_t launch_size_order(int64_t n_sets, const int64_t* rp, void* scratch, size_t scratch_bytes,
+                             const uint32_t** order, hipStream_t st);
+
+// The context's device tables for t, its device, its number of compute units
+// and its options.
+int ctx_spec(dms_ctx c, uint32_t t, const SpecTables** out);
+int ctx_device(dms_ctx c);
+int ctx_n_cu(dms_ctx c);
+double ctx_phi0(dms_ctx c);
+double ctx_phi_max(dms_ctx c);
+int ctx_hash(dms_ctx c);
+}  // namespace dms

@@ -23,42 +23,8 @@
 
 #include "../../include/dms.h"
 #include "dms_internal.h"
+#include "dms_launch.h"
 
-namespace dms {
-hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                              const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                              uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                              double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
-hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
-size_t fast_lds_bytes(int k, int waves);
-hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
-                                    const int32_t* idx, const double* w, int k, uint32_t* out_u32,
-                                    uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                                    double* out_rank, double phi0, double phi_max,
-                                    unsigned long long* counter, int blocks, const void* parts,
-                                    int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    int hash, hipStream_t st);
-hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
-                             hipStream_t st);
-size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
-int hamming_blocks(int64_t n_db, int n_cu);
-hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
-                          int64_t n_q, int topk, int64_t* out_ids, int32_t* out_dist,
-                          uint64_t* partial, int n_blocks, hipStream_t st);
-
-// Provided by dms_api.cpp: the context's device tables for t, its device, its
-// number of compute units and its phi options.
-int ctx_spec(dms_ctx c, uint32_t t, const SpecTables** out);
-int ctx_device(dms_ctx c);
-int ctx_n_cu(dms_ctx c);
-double ctx_phi0(dms_ctx c);
-double ctx_phi_max(dms_ctx c);
-int ctx_hash(dms_ctx c);
-}  // namespace dms
 
 namespace {
 
@@ -238,7 +204,7 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
                                                   s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
                                                   dms::ctx_phi_max(S->ctx), s.d_counter + g,
                                                   2 * dms::ctx_n_cu(S->ctx), dp, n_parts, dh, db,
-                                                  n_parts > 0 ? split : 0, dms::ctx_hash(S->ctx), st);
+                                                  n_parts > 0 ? split : 0, nullptr, dms::ctx_hash(S->ctx), st);
             part_base += n_parts;
             part_heavy += n_heavy;
             bucket_base += n_parts * 2 * (int64_t)k;

@@ -253,7 +253,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             uint32_t* out_u32, uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
             double* out_rank, uint64_t* out_keys, double phi0, double phi_max,
             unsigned long long* next_set, const Part* __restrict__ parts, int64_t n_parts,
-            HeavySet* heavy, uint64_t* partial, int64_t split)
+            HeavySet* heavy, uint64_t* partial, int64_t split, const uint32_t* __restrict__ order)
 {
     constexpr bool LSH = MODE == kModeLsh;
     constexpr bool BK = MODE == kModeBottomK;
@@ -805,7 +805,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 if (!wave_all(filled)) status = run(b0, b1, S, 2.0 * phi0, phi0 / S, false);
             }
         } else {
-            set = item - n_parts;
+            set = order ? (int64_t)order[item - n_parts] : item - n_parts;  // largest sets first
             const int64_t b0 = rp[set], b1 = rp[set + 1];
             if (MODE == kModeMinhash && split > 0 && b1 - b0 > split) continue;  // served by its parts
             const RowInfo ri = scan_row(wts, b0, b1, lane);
@@ -859,7 +859,7 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
                                             const double*, int, int, uint32_t*, uint64_t*, int8_t*,     \
                                             uint64_t*, double*, uint64_t*, double, double,             \
                                             unsigned long long*, const Part*, int64_t, HeavySet*,      \
-                                            uint64_t*, int64_t);
+                                            uint64_t*, int64_t, const uint32_t*);
 DMS_FAST_KERNEL(kModeMinhash, kHashMix)
 DMS_FAST_KERNEL(kModeLsh, kHashMix)
 DMS_FAST_KERNEL(kModeBottomK, kHashMix)
@@ -1019,7 +1019,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    int hash, hipStream_t st)
+                                    const uint32_t* order, int hash, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeMinhash, k, 1);
@@ -1031,7 +1031,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
-                       (HeavySet*)heavy, partial, split);
+                       (HeavySet*)heavy, partial, split, order);
     return hipGetLastError();
 }
 
@@ -1043,13 +1043,14 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
 {
     return launch_sketch_fast_split(sp, n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s,
                                     out_rank, phi0, phi_max, counter, blocks, nullptr, 0, nullptr,
-                                    nullptr, 0, hash, st);
+                                    nullptr, 0, nullptr, hash, st);
 }
 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
-                           unsigned long long* counter, int blocks, int hash, hipStream_t st)
+                           unsigned long long* counter, int blocks, const uint32_t* order, int hash,
+                           hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeLsh, L, K);
@@ -1062,14 +1063,15 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
                        (const Part*)nullptr, (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr,
-                       (int64_t)0);
+                       (int64_t)0, order);
     return hipGetLastError();
 }
 
 hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,
-                               unsigned long long* counter, int blocks, int hash, hipStream_t st)
+                               unsigned long long* counter, int blocks, const uint32_t* order, int hash,
+                               hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeBottomK, k, 1);
@@ -1081,7 +1083,7 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        out_s, out_rank, (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)nullptr,
-                       (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0);
+                       (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0, order);
     return hipGetLastError();
 }
 

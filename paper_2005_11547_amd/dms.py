@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libdms.so")
 DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
 SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
-OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH = 0, 1, 2, 3, 4, 5, 6
+OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH, OPT_ORDER = (
+    0, 1, 2, 3, 4, 5, 6, 7)
 HASH_MIX, HASH_TAB = 0, 1
 FMT_U32, FMT_1BIT = 0, 1
 
