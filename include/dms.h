@@ -54,7 +54,9 @@ typedef int32_t dms_status;
 #define DMS_OPT_SPLIT_NNZ 4 /* fast engine: sets with more nonzeros are shared by several
                                wavefronts, one part of at most this many nonzeros each
                                (default 4096; 0 disables).  The call then reads two counts back
-                               from the device before its main launch. */
+                               from the device before its main launch; with 0, a sketch call only
+                               enqueues kernels and, once an eager call of the same size has sized
+                               the context's scratch, can be captured into a HIP graph. */
 #define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
 #define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
                                Unlike the other options it changes the outputs: sketches made
