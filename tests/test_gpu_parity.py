@@ -126,6 +126,22 @@ def test_lsh_edge_rows(torch, ctx):
         assert np.array_equal(out["keys"].cpu().numpy().view(np.uint64), ref["keys"]), (L, K)
 
 
+def test_lsh_more_than_64_tables(torch, ctx):
+    # past 64 tables the insertion-election slots live after the table counts
+    # instead of sharing the expansion marks
+    rp, idx, w = WL.lsh_L64K8(seed=91, n_sets=300)
+    rows = [(idx[rp[q]:rp[q + 1]], w[rp[q]:rp[q + 1]]) for q in range(len(rp) - 1)]
+    rows += [([], []), ([4, 4, 9], [0.3, 0.7, 1.0]), ([1], [3.0])]
+    rp, idx, w = WL.csr_from_rows(rows)
+    for L, K in ((64, 3), (65, 2), (128, 4), (200, 3), (1024, 1)):
+        print(f"[parity] lsh L={L} K={K}", flush=True)
+        out = ctx.lsh(*_dev(torch, rp, idx, w), L, K)
+        torch.cuda.synchronize()
+        ref = O.lsh_csr(rp, idx, w, L, K, SEED)
+        assert np.array_equal(out["status"].cpu().numpy(), ref["status"]), (L, K)
+        assert np.array_equal(out["keys"].cpu().numpy().view(np.uint64), ref["keys"]), (L, K)
+
+
 def test_jaccard_estimates(torch, ctx):
     from paper_2005_11547_amd import dms
     rng = np.random.default_rng(3)
