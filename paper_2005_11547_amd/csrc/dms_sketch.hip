@@ -199,21 +199,61 @@ struct LshTables {
         if (c < K) cnt[l] = c + 1;
     }
 
-    // Called by all 64 lanes; lanes with `has` insert their dart.  Lanes aiming
-    // at the same table take turns (the smallest lane id wins each round);
-    // different tables are filled in parallel.
+    // K = 8: the row's eight entries are read at once (independent loads), the
+    // position is found in registers and the whole row is rewritten.  Entries
+    // past the count are never taken for darts.
+    __device__ void insert_row8(uint32_t l, uint64_t rb, uint64_t s) const
+    {
+        uint64_t* r = rank + (size_t)l * 8;
+        uint64_t* v = sval + (size_t)l * 8;
+        const int c = cnt[l];
+        uint64_t R[8], V[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            R[m] = r[m];
+            V[m] = v[m];
+        }
+        int pos = 0;
+        bool dup = false;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const bool in = m < c;
+            dup |= in && R[m] == rb && V[m] == s;  // the same dart again (repeated element id)
+            pos += (in && (R[m] < rb || (R[m] == rb && V[m] < s))) ? 1 : 0;
+        }
+        if (dup || pos >= 8) return;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            r[m] = m < pos ? R[m] : m == pos ? rb : R[m > 0 ? m - 1 : 0];
+            v[m] = m < pos ? V[m] : m == pos ? s : V[m > 0 ? m - 1 : 0];
+        }
+        if (c < 8) cnt[l] = (uint8_t)(c + 1);
+    }
+
+    // Called by all 64 lanes; lanes with `has` insert their dart.  A dart above
+    // a full table's largest is dropped at once (later insertions only lower
+    // that bound).  The others draw tickets from their table's counter; step i
+    // inserts the darts holding ticket i, at most one per table, so different
+    // tables fill in parallel and no table is written twice in a step.  The
+    // order of insertions does not change a table's final K smallest darts.
     __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s, int lane) const
     {
+        (void)lane;
         bool pending = has;
-        while (wave_any(pending)) {
-            if (pending) __hip_atomic_store(&owner[l], 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            wave_sync();
-            if (pending) __hip_atomic_fetch_min(&owner[l], lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            wave_sync();
-            const bool mine = pending &&
-                __hip_atomic_load(&owner[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
-            if (mine) {
-                insert_one(l, rb, s);
+        if (pending && cnt[l] >= K) {
+            const uint64_t mr = rank[(size_t)l * K + K - 1], ms = sval[(size_t)l * K + K - 1];
+            pending = rb < mr || (rb == mr && s <= ms);
+        }
+        if (!wave_any(pending)) return;
+        if (pending) __hip_atomic_store(&owner[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        wave_sync();
+        int ticket = 0;
+        if (pending)
+            ticket = __hip_atomic_fetch_add(&owner[l], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int step = 0; wave_any(pending); ++step) {
+            if (pending && ticket == step) {
+                if (K == 8) insert_row8(l, rb, s);
+                else insert_one(l, rb, s);
                 pending = false;
             }
             wave_sync();
