@@ -9,7 +9,10 @@
 //               k-th best for that query is appended to a per-query candidate
 //               list in LDS; after every tile of rows the lists are folded into
 //               each query's sorted top-k.  The block writes its top-k per query.
-// merge kernel: one block per query selects the k smallest keys of all blocks.
+// merge kernel: one block per query selects the k smallest keys of all blocks:
+//               for k <= 16 each thread keeps the 16 smallest of its share of
+//               the keys in registers and one wave selects from those in LDS;
+//               larger k: one wave selects directly from global memory.
 // Keys are unique (row ids differ), so (distance, id) order is total.
 #include "dms_device.h"
 
@@ -94,14 +97,17 @@ hamming_scan_kernel(const uint64_t* __restrict__ db, int64_t n_db, int words,
             const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
             if (have && key < thr[q]) {
                 const uint32_t slot = atomicAdd(&ncand[q], 1u);
-                cand[q][slot] = key;  // slot < kTile: at most one candidate per thread per tile
+                cand[q][slot] = key;  // slot < ncand before the tile + kTile <= kCand - topk
             }
         }
         __syncthreads();
-        // fold candidates into each query's top-k (one wave per query)
+        // fold candidates into each query's top-k (one wave per query) once the
+        // list could not take another tile, and after the last tile; until then
+        // the threshold stays that of the last fold (looser, still exact)
+        const bool last = base + kTile >= r_end;
         for (int q = wave; q < nq; q += blockDim.x / 64) {
             const int n = (int)ncand[q];
-            if (n == 0) continue;
+            if (n == 0 || (!last && n + kTile + topk <= kCand)) continue;
             for (int i = lane; i < topk; i += kWave) cand[q][n + i] = best[q][i];
             wave_sync();
             wave_select(cand[q], n + topk, topk, merged[q], lane);
@@ -118,6 +124,44 @@ hamming_scan_kernel(const uint64_t* __restrict__ db, int64_t n_db, int words,
     for (int i = tid; i < nq * topk; i += blockDim.x) {
         const int q = i / topk, r = i % topk;
         partial[((q0 + q) * gridDim.x + blockIdx.x) * (int64_t)topk + r] = best[q][r];
+    }
+}
+
+// grid: n_q blocks of 256 threads; topk <= kSmallTopk.
+constexpr int kSmallTopk = 16;
+__global__ void __launch_bounds__(256)
+hamming_merge_small_kernel(const uint64_t* __restrict__ partial, int n_blocks, int topk,
+                           int64_t* __restrict__ out_ids, int32_t* __restrict__ out_dist)
+{
+    __shared__ uint64_t pool[256 * kSmallTopk];
+    __shared__ uint64_t res[kSmallTopk];
+    const int64_t q = blockIdx.x;
+    const int n = n_blocks * topk;
+    const uint64_t* keys = partial + q * (int64_t)n;
+    uint64_t best[kSmallTopk];  // ascending
+#pragma unroll
+    for (int j = 0; j < kSmallTopk; ++j) best[j] = kNoKey;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        uint64_t v = keys[i];
+#pragma unroll
+        for (int j = 0; j < kSmallTopk; ++j) {  // one pass of insertion: best stays sorted
+            const uint64_t lo = v < best[j] ? v : best[j];
+            v = v < best[j] ? best[j] : v;
+            best[j] = lo;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSmallTopk; ++j) pool[threadIdx.x * kSmallTopk + j] = best[j];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        wave_select(pool, 256 * kSmallTopk, topk, res, lane);
+        wave_sync();
+        for (int r = lane; r < topk; r += kWave) {
+            const uint64_t v = res[r];
+            out_ids[q * topk + r] = v == kNoKey ? -1 : (int64_t)(uint32_t)v;
+            out_dist[q * topk + r] = v == kNoKey ? -1 : (int32_t)(v >> 32);
+        }
     }
 }
 
@@ -194,8 +238,12 @@ hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uin
                            n_q, topk, rpb, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hamming_merge_kernel, dim3((unsigned)n_q), dim3(64), 0, st, partial, n_blocks,
-                       topk, out_ids, out_dist);
+    if (topk <= kSmallTopk)
+        hipLaunchKernelGGL(hamming_merge_small_kernel, dim3((unsigned)n_q), dim3(256), 0, st, partial,
+                           n_blocks, topk, out_ids, out_dist);
+    else
+        hipLaunchKernelGGL(hamming_merge_kernel, dim3((unsigned)n_q), dim3(64), 0, st, partial, n_blocks,
+                           topk, out_ids, out_dist);
     return hipGetLastError();
 }
 

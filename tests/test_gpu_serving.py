@@ -32,7 +32,11 @@ def _bits(rng, n, words):
 
 @pytest.mark.parametrize("words,n_db,n_q,topk", [(16, 50_000, 40, 10), (1, 3000, 17, 10),
                                                   (4, 20_000, 33, 64), (16, 5, 3, 10),
-                                                  (16, 1, 1, 1), (7, 9000, 16, 5)])
+                                                  (16, 1, 1, 1), (7, 9000, 16, 5),
+                                                  # the full grid of row slices: 512 partial
+                                                  # top-k lists per query to merge
+                                                  (16, 600_000, 4, 10), (16, 600_000, 3, 16),
+                                                  (16, 600_000, 2, 17)])
 def test_hamming_topk_matches_brute_force(torch, ctx, words, n_db, n_q, topk):
     print(f"[search] words={words} n_db={n_db} n_q={n_q} topk={topk}", flush=True)
     rng = np.random.default_rng(words * 1000 + n_db)
