@@ -62,7 +62,7 @@ def calibrate_mixer(ctx, torch, n_cu):
     return mixers / (ms * 1e-3)
 
 
-def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=256):
+def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=128):
     """The serving workload: Poisson arrivals at `rate`, half sketch-only requests
     (k uniform in {64, 256, 1024}), half 1-bit k = 1024 sketch + top-10 Hamming
     search against a device-resident database of n_db sketched sets; 1% of the
@@ -376,7 +376,7 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
-    ap.add_argument("--serving-split", type=int, default=256,
+    ap.add_argument("--serving-split", type=int, default=128,
                     help="serving: sets with more nonzeros are shared by several wavefronts (0: never)")
     ap.add_argument("--table1", action="store_true",
                     help="time the paper's Table 1 shapes instead (GPU, oracle, paper) and exit")

@@ -387,7 +387,7 @@ class Server:
     database of 1-bit k = 1024 sketches."""
 
     def __init__(self, ctx: Context, db, topk=10, max_batch=256, max_inflight=4,
-                 max_batch_nnz=1 << 20, max_set_nnz=4096, split_nnz=256):
+                 max_batch_nnz=1 << 20, max_set_nnz=4096, split_nnz=128):
         import numpy as np
         self.ctx, self.db, self.topk = ctx, db, topk
         cfg = ServerConfig(max_batch, max_inflight, max_batch_nnz, max_set_nnz, 16, topk, split_nnz)
