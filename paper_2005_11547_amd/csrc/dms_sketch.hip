@@ -171,7 +171,8 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
 }
 
 // (L,K) LSH tables of one wave: table l holds cnt[l] <= K darts sorted by
-// (rank, id hash).  insert_one is run by one lane per table at a time.
+// (rank, id hash).  insert_one and insert_row8 are run by one lane per table
+// at a time; owner[l] is the table's ticket counter.
 struct LshTables {
     uint64_t* rank;
     uint64_t* sval;
@@ -236,9 +237,8 @@ struct LshTables {
     // inserts the darts holding ticket i, at most one per table, so different
     // tables fill in parallel and no table is written twice in a step.  The
     // order of insertions does not change a table's final K smallest darts.
-    __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s, int lane) const
+    __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s) const
     {
-        (void)lane;
         bool pending = has;
         if (pending && cnt[l] >= K) {
             const uint64_t mr = rank[(size_t)l * K + K - 1], ms = sval[(size_t)l * K + K - 1];
@@ -527,7 +527,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         uint64_t s = 0;
                         if (acc) s = H(a ^ KS ^ j);
                         if (LSH) {
-                            T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, lane);
+                            T.insert(acc, bucket_of(s, (uint32_t)k), rb, s);
                         } else if (BK) {
                             bool keep = acc && (rb < cut_r || (rb == cut_r && s < cut_s));
                             uint64_t bk = __ballot(keep);
