@@ -51,9 +51,9 @@ jaccard_1bit_kernel(int64_t n_pairs, const uint64_t* __restrict__ a, const uint6
 // Pairs whose rows are a power-of-two number of 16-byte vectors (four u32
 // minhashes or two 64-bit words): G = min(vectors, 64) lanes share a pair, each
 // loading whole vectors of a and b, and 64 / G pairs share a wave; the group's
-// count is summed by butterflies within the group.  `bits` = 0 selects u32
-// minhashes; otherwise rows are packed fingerprints of `bits` bits (1 for the
-// 1-bit sketch), `bits` dividing 64, bits past k * bits ignored.
+// count is summed by butterflies within the group.  FMT 0: u32 minhashes;
+// 1: 1-bit sketches; 2: packed fingerprints of `bits` bits, `bits` dividing 64.
+// Bits past k * bits in a row's last word are ignored.
 template <int FMT>  // 0: u32 minhashes, 1: 1-bit sketch, 2: b-bit fingerprints
 __global__ void __launch_bounds__(256)
 pair_vec_kernel(int64_t n_pairs, const uint4* __restrict__ a, const uint4* __restrict__ b, int k, int bits,

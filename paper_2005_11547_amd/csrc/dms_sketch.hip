@@ -148,8 +148,8 @@ __host__ __device__ constexpr uint32_t bk_cap(int k)
 }
 
 // LSH table bookkeeping after the L sorted lists: one count byte per table
-// (K <= 64), padded to 8 bytes, then -- only past 64 tables -- the owner slots
-// of the insertion election; up to 64 tables borrow the expansion marks, which
+// (K <= 64), padded to 8 bytes, then -- only past 64 tables -- the tables'
+// ticket counters; up to 64 tables borrow the expansion marks for them, which
 // are never live during an accept round.
 __host__ __device__ constexpr size_t lsh_aux_bytes(int L)
 {
@@ -172,12 +172,12 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
 
 // (L,K) LSH tables of one wave: table l holds cnt[l] <= K darts sorted by
 // (rank, id hash).  insert_one and insert_row8 are run by one lane per table
-// at a time; owner[l] is the table's ticket counter.
+// at a time; ticket[l] is the table's ticket counter.
 struct LshTables {
     uint64_t* rank;
     uint64_t* sval;
     uint8_t* cnt;
-    int32_t* owner;
+    int32_t* ticket;
     int K;
 
     __device__ void insert_one(uint32_t l, uint64_t rb, uint64_t s) const
@@ -245,13 +245,13 @@ struct LshTables {
             pending = rb < mr || (rb == mr && s <= ms);
         }
         if (!wave_any(pending)) return;
-        if (pending) __hip_atomic_store(&owner[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (pending) __hip_atomic_store(&ticket[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         wave_sync();
-        int ticket = 0;
+        int mine = 0;
         if (pending)
-            ticket = __hip_atomic_fetch_add(&owner[l], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            mine = __hip_atomic_fetch_add(&ticket[l], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         for (int step = 0; wave_any(pending); ++step) {
-            if (pending && ticket == step) {
+            if (pending && mine == step) {
                 if (K == 8) insert_row8(l, rb, s);
                 else insert_one(l, rb, s);
                 pending = false;
@@ -325,7 +325,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     T.rank = bin_rank;
     T.sval = bin_s;
     T.cnt = reinterpret_cast<uint8_t*>(bin_s + k * K);
-    T.owner = k <= kWave ? &at<int32_t>(wb, kOffMark, 0)
+    T.ticket = k <= kWave ? &at<int32_t>(wb, kOffMark, 0)
                          : reinterpret_cast<int32_t*>(T.cnt + ((k + 7) / 8) * 8);
     T.K = K;
 
