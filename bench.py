@@ -421,10 +421,11 @@ def main():
         # batch before any timing; outputs do not depend on it
         t0 = time.perf_counter()
         phi0, split = ctx.autotune(d_rp, d_idx, d_w, k)
-        tuned = {"phi0": phi0, "split_nnz": split, "seconds": time.perf_counter() - t0}
+        tuned = {"phi0": phi0, "split_nnz": split, "order": ctx.get_option(dms.OPT_ORDER),
+                 "seconds": time.perf_counter() - t0}
         log(f"autotune: {tuned}")
     schedule = {"phi0": ctx.get_option(dms.OPT_PHI0), "split_nnz": ctx.get_option(dms.OPT_SPLIT_NNZ),
-                "autotuned": tuned is not None}
+                "largest_first": bool(ctx.get_option(dms.OPT_ORDER)), "autotuned": tuned is not None}
 
     def step():
         ctx.dms_sketch_csr(n_sets, d_rp, d_idx, d_w, k, out_u32, out_bits, out_status)
@@ -547,8 +548,9 @@ def main():
             t0 = time.perf_counter()
             tctx = Context(WL.HASH_SEED, engine=engine)
             phi0, split = tctx.autotune(d_rp, d_idx, d_w, k)
+            order = tctx.get_option(dms.OPT_ORDER)
             tctx.close()
-            result["secondary"]["autotune"] = {"phi0": phi0, "split_nnz": split,
+            result["secondary"]["autotune"] = {"phi0": phi0, "split_nnz": split, "order": order,
                                                "seconds": time.perf_counter() - t0}
             log(f"autotune: {result['secondary']['autotune']}")
     if args.serving_seconds > 0:

@@ -128,8 +128,9 @@ dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
  * Autotuner for dms_sketch_csr: times the sketch of a prefix of the batch
  * (its first min(n_sets, 2^28/k) rows, so the rows should be in no particular
  * order) under candidate schedules -- first phi in {1, 1.15, 1.3, 1.5, 1.8},
- * then split thresholds in {0, 1024, 4096, 16384} -- and sets DMS_OPT_PHI0 and
- * DMS_OPT_SPLIT_NNZ on the context to the fastest.  Outputs never depend on
+ * then split thresholds in {0, 1024, 4096, 16384}, then both DMS_OPT_ORDER
+ * values -- and sets DMS_OPT_PHI0, DMS_OPT_SPLIT_NNZ and DMS_OPT_ORDER on the
+ * context to the fastest.  Outputs never depend on
  * either (Theorem 1's output is independent of the schedule; parts merge
  * exactly).  Synchronizes the stream; allocates and frees its own buffers.
  *   out_phi0, out_split: host double* or NULL, receive the chosen values

@@ -813,7 +813,9 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         return best;
     };
     const double keep_phi0 = c->phi0, keep_split = c->split_nnz;
+    const int keep_order = c->order;
     double best_phi0 = keep_phi0, best_split = keep_split;
+    int best_order = keep_order;
     if (rc == DMS_OK) {
         // coordinate search: the first phi, then the split threshold
         const double phis[] = {1.0, 1.15, 1.3, 1.5, 1.8};
@@ -829,6 +831,10 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
             const float ms = trial(best_phi0, sp);
             if (ms < best) { best = ms; best_split = sp; }
         }
+        // then the order in which waves take the sets
+        c->order = 1 - keep_order;
+        const float ms = trial(best_phi0, best_split);
+        if (ms < best) best_order = c->order;
     }
     (void)hipFree(out);
     (void)hipFree(st);
@@ -836,6 +842,7 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     if (e1) (void)hipEventDestroy(e1);
     c->phi0 = rc == DMS_OK ? best_phi0 : keep_phi0;
     c->split_nnz = rc == DMS_OK ? best_split : keep_split;
+    c->order = rc == DMS_OK ? best_order : keep_order;
     if (rc != DMS_OK) return rc;
     if (out_phi0) *out_phi0 = best_phi0;
     if (out_split) *out_split = best_split;

@@ -206,5 +206,6 @@ def test_autotune_picks_a_candidate_and_changes_no_output(torch):
     phi0, split = c.autotune(*d, 256)
     assert phi0 in (1.0, 1.15, 1.3, 1.5, 1.8) and split in (0.0, 1024.0, 4096.0, 16384.0)
     assert c.get_option(dms.OPT_PHI0) == phi0 and c.get_option(dms.OPT_SPLIT_NNZ) == split
+    assert c.get_option(dms.OPT_ORDER) in (0.0, 1.0)
     _check_sketch(torch, c, rp[:401], idx[:rp[400]], w[:rp[400]], 256, f"after autotune phi0={phi0} split={split}")
     c.close()
