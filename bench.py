@@ -115,6 +115,33 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=12
     return res
 
 
+def plain_engine_run(torch, d, k, out_u32, out_bits, steps=2):
+    """The same batch through the plain engine (one launch, one wave per set,
+    one lane per nonzero): its time per batch, and whether all of its outputs
+    equal the persistent engine's."""
+    from paper_2005_11547_amd import Context, dms
+    n = out_u32.shape[0]
+    c = Context(WL.HASH_SEED, engine=dms.ENGINE_PLAIN)
+    u32 = torch.empty_like(out_u32)
+    bits = torch.empty_like(out_bits)
+    st = torch.empty(n, dtype=torch.int8, device="cuda")
+    c.dms_sketch_csr(n, d[0], d[1], d[2], k, u32, bits, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        c.dms_sketch_csr(n, d[0], d[1], d[2], k, u32, bits, st)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    same = bool(torch.equal(u32, out_u32) and torch.equal(bits, out_bits))
+    c.close()
+    res = {"ms_per_step": ms, "sets_per_s": n / (ms * 1e-3), "identical_to_persistent_engine": same}
+    log(f"plain engine: {res}")
+    del u32, bits, st
+    return res
+
+
 def secondary_runs(ctx, torch, steps=3, main=None):
     """Throughput of the other batch workloads (k = 1024 uneven batching,
     (L,K) = (64,8) LSH keys, bottom-k sketches with k = 256 of the main batch,
@@ -540,8 +567,10 @@ def main():
         del src, dst
     if args.secondary and args.workload == "batch_k256":
         fp = fingerprint_runs(ctx, torch, out_u32, out_bits, k)
+        plain = plain_engine_run(torch, (d_rp, d_idx, d_w), k, out_u32, out_bits)
         result["secondary"] = secondary_runs(ctx, torch, main=(rp, idx, w))
         result["secondary"]["bbit_b8"] = fp
+        result["secondary"]["plain_engine_batch_k256"] = plain
         result["secondary"]["lsh_index_L64K8"] = index_run(ctx, torch)
         if not args.autotune:
             # what the autotuner picks for this batch (on a context of its own)
