@@ -142,11 +142,12 @@ def plain_engine_run(torch, d, k, out_u32, out_bits, steps=2):
     return res
 
 
-def secondary_runs(ctx, torch, steps=3, main=None):
+def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
     """Throughput of the other batch workloads (k = 1024 uneven batching,
     (L,K) = (64,8) LSH keys, bottom-k sketches with k = 256 of the main batch,
     and the main batch under the tabulation-hash variant), each checked bit for
-    bit on a row sample."""
+    bit on a row sample; for the uneven batch also the fraction of the
+    int-VALU peak, from the oracle's enumeration counts on every 20th set."""
     from oracle import oracle as O
     from paper_2005_11547_amd import Context, dms, to_device
     res = {}
@@ -209,6 +210,20 @@ def secondary_runs(ctx, torch, steps=3, main=None):
                          np.array_equal(rk[torch.from_numpy(rows).cuda()].cpu().numpy(), ref["rank"]))
         res[name] = {"sets_per_s": n / (ms * 1e-3), "nnz_per_s": float(rp[-1]) / (ms * 1e-3),
                      "ms_per_step": ms, "n_sets": n, "bit_exact_sample": {"sets_checked": 200, "exact": exact}}
+        if kind == "sketch" and c_mix is not None:
+            # algorithmic work of the batch from the oracle's counts on every 20th set
+            rows = np.arange(0, n, 20)
+            sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
+            sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
+            sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
+            r = O.sketch_csr(sub_rp, sub_idx, sub_w, 1024, WL.HASH_SEED, full=True)
+            same = bool(np.array_equal(out[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32), r["u32"]))
+            H, ops = algorithmic_work(r["counters"], c_mix)
+            achieved = float(ops.mean()) * n / (ms * 1e-3) / 1e12
+            res[name]["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
+                                     "unit": "T int32 lane-op/s", "frac": achieved / PEAK_INT_TOPS,
+                                     "mixers_per_set": float(H.mean()),
+                                     "sample": f"every 20th set ({len(rows)} sets), bit-exact: {same}"}
         log(f"{name}: {res[name]}")
         del d, out
     return res
@@ -568,7 +583,7 @@ def main():
     if args.secondary and args.workload == "batch_k256":
         fp = fingerprint_runs(ctx, torch, out_u32, out_bits, k)
         plain = plain_engine_run(torch, (d_rp, d_idx, d_w), k, out_u32, out_bits)
-        result["secondary"] = secondary_runs(ctx, torch, main=(rp, idx, w))
+        result["secondary"] = secondary_runs(ctx, torch, main=(rp, idx, w), c_mix=c_mix)
         result["secondary"]["bbit_b8"] = fp
         result["secondary"]["plain_engine_batch_k256"] = plain
         result["secondary"]["lsh_index_L64K8"] = index_run(ctx, torch)
