@@ -53,7 +53,9 @@ typedef int32_t dms_status;
 #define DMS_OPT_PHI_MAX 3   /* give up with DMS_SET_RANGE beyond this phi (default 2^20) */
 #define DMS_OPT_SPLIT_NNZ 4 /* fast engine: sets with more nonzeros are shared by several
                                wavefronts, one part of at most this many nonzeros each
-                               (default 4096; 0 disables).  The call then reads two counts back
+                               (default 4096; 0 disables, and then every set must have fewer
+                               than 2^32 nonzeros: queues name elements by 32-bit offsets within
+                               the set or part).  The call then reads two counts back
                                from the device before its main launch; with 0, a sketch call only
                                enqueues kernels and, once an eager call of the same size has sized
                                the context's scratch, can be captured into a HIP graph. */
