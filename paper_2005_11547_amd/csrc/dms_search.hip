@@ -69,6 +69,7 @@ hamming_scan_kernel(const uint64_t* __restrict__ db, int64_t n_db, int words,
     __shared__ uint64_t thr[kQG];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool vec16 = (words % 2) == 0 && ((uintptr_t)db & 15) == 0;
     const int64_t q0 = (int64_t)blockIdx.y * kQG;
     const int nq = (int)((n_q - q0) < kQG ? (n_q - q0) : kQG);
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
@@ -86,8 +87,19 @@ hamming_scan_kernel(const uint64_t* __restrict__ db, int64_t n_db, int words,
         const int64_t row = base + tid;
         const bool have = row < r_end;
         uint64_t w[WMAX];
+        if (vec16) {  // even words on a 16-byte aligned database: 16-byte loads
+            const uint4* r4 = reinterpret_cast<const uint4*>(db + (have ? row : 0) * words);
 #pragma unroll
-        for (int j = 0; j < WMAX; ++j) w[j] = (have && j < words) ? db[row * words + j] : 0ull;
+            for (int j = 0; j < WMAX; j += 2) {
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (have && j < words) v = r4[j / 2];
+                w[j] = ((uint64_t)v.y << 32) | v.x;
+                if (j + 1 < WMAX) w[j + 1] = ((uint64_t)v.w << 32) | v.z;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < WMAX; ++j) w[j] = (have && j < words) ? db[row * words + j] : 0ull;
+        }
         for (int q = 0; q < nq; ++q) {
             const uint64_t* qw = queries + (q0 + q) * words;
             uint32_t d = 0;
