@@ -368,6 +368,35 @@ dms_status dms_server_replay(dms_server s, int64_t n_req, const double* arrival_
                              uint32_t* out_sketch, int8_t* out_status, int64_t* out_ids,
                              int32_t* out_dist, double* out_latency_s, double* out_stats);
 
+/*
+ * Online use of the same server: requests are submitted as they come and the
+ * answers collected by polling.  A server serves either replays or online
+ * requests at a time (dms_server_replay returns DMS_EINVAL while online
+ * requests are pending).  Not thread-safe: one thread drives a server.
+ *
+ * dms_server_submit copies the request's set (host idx[nnz], w[nnz]) into the
+ * server and returns its id (0, 1, 2, ... in submission order).  Errors:
+ * DMS_EINVAL (kind, k or nnz outside the configured limits).
+ *
+ * dms_server_poll collects finished batches, admits waiting requests into free
+ * slots (in submission order, within each slot's memory budget) and returns up
+ * to max_out answers in completion order.  With wait_ms > 0 it waits up to that
+ * long for a first answer while requests are in flight.  Host outputs, row n for
+ * the n-th answer (each may be NULL but out_id):
+ *   out_id[max_out]                    request id
+ *   out_status[max_out]                DMS_SET_*
+ *   out_sketch[max_out*1024]           the request's k minhashes at out_sketch[n*1024 ...]
+ *   out_ids, out_dist[max_out*topk]    search answers (rows of search requests only)
+ *   out_latency_s[max_out]             answer time minus submission time
+ *   *n_out                             answers written
+ * Errors: DMS_EINVAL, DMS_EHIP, DMS_ESPEC.
+ */
+dms_status dms_server_submit(dms_server s, int32_t kind, int32_t k, int64_t nnz, const int32_t* idx,
+                             const double* w, int64_t* out_id);
+dms_status dms_server_poll(dms_server s, int32_t wait_ms, int64_t max_out, int64_t* out_id,
+                           int8_t* out_status, uint32_t* out_sketch, int64_t* out_ids, int32_t* out_dist,
+                           double* out_latency_s, int64_t* n_out);
+
 /* Wait until all work queued on the context's stream is done. */
 dms_status dms_sync(dms_ctx ctx);
 

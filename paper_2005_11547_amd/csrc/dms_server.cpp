@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <unordered_map>
 #include <thread>
 #include <vector>
 
@@ -63,6 +64,29 @@ struct Slot {
     std::vector<int64_t> out_off;    // offset of each row's minhashes in d_u32
     std::vector<int64_t> query_row;  // batch row of each search query
     int64_t n_u32 = 0, n_q = 0;
+    // online batches: the request id and k of each batch-local request index
+    std::vector<int64_t> online_id;
+    std::vector<int32_t> online_k;
+};
+
+// A request submitted online, waiting for a slot or in flight.
+struct OnlineReq {
+    int32_t kind = 0, k = 0;
+    std::vector<int32_t> idx;
+    std::vector<double> w;
+    double t_submit = 0.0;
+};
+
+// An answer waiting to be polled.
+struct OnlineDone {
+    int64_t id = 0;
+    int32_t k = 0;
+    int8_t status = 0;
+    bool search = false;
+    std::vector<uint32_t> sketch;
+    std::vector<int64_t> ids;
+    std::vector<int32_t> dist;
+    double latency = 0.0;
 };
 
 }  // namespace
@@ -74,6 +98,13 @@ struct dms_server_s {
     int64_t n_db = 0;
     int hamming_blocks = 1;
     std::vector<Slot> slots;
+    // online use (dms_server_submit / dms_server_poll)
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    int64_t next_id = 0;
+    std::deque<int64_t> waiting;                      // submitted, not yet in a batch
+    std::unordered_map<int64_t, OnlineReq> requests;  // submitted, not yet answered
+    std::deque<OnlineDone> answers;                   // answered, not yet polled
+    int64_t in_flight = 0;                            // online requests on the GPU
 };
 
 namespace {
@@ -324,6 +355,7 @@ dms_status dms_server_replay(dms_server S, int64_t n_req, const double* arrival_
 {
     if (!S || n_req < 0 || (n_req > 0 && (!arrival_s || !kind || !kval || !row_ptr || !idx || !w)))
         return DMS_EINVAL;
+    if (!S->requests.empty()) return DMS_EINVAL;  // online requests are still pending
     const dms_server_config& C = S->cfg;
     for (int64_t r = 0; r < n_req; ++r) {
         const int64_t n = row_ptr[r + 1] - row_ptr[r];
@@ -415,6 +447,124 @@ dms_status dms_server_replay(dms_server S, int64_t n_req, const double* arrival_
         out_stats[5] = batches ? (double)batch_rows / (double)batches : 0.0;
         out_stats[6] = total;
     }
+    return DMS_OK;
+}
+
+dms_status dms_server_submit(dms_server S, int32_t kind, int32_t k, int64_t nnz, const int32_t* idx,
+                             const double* w, int64_t* out_id)
+{
+    if (!S || !out_id || nnz < 0 || (nnz > 0 && (!idx || !w))) return DMS_EINVAL;
+    const dms_server_config& C = S->cfg;
+    if ((k != 64 && k != 256 && k != 1024) || nnz > C.max_set_nnz ||
+        (kind != DMS_REQ_SKETCH && kind != DMS_REQ_SEARCH) || (kind == DMS_REQ_SEARCH && k != 1024))
+        return DMS_EINVAL;
+    OnlineReq r;
+    r.kind = kind;
+    r.k = k;
+    r.idx.assign(idx, idx + nnz);
+    r.w.assign(w, w + nnz);
+    r.t_submit = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+    const int64_t id = S->next_id++;
+    S->requests.emplace(id, std::move(r));
+    S->waiting.push_back(id);
+    *out_id = id;
+    return DMS_OK;
+}
+
+dms_status dms_server_poll(dms_server S, int32_t wait_ms, int64_t max_out, int64_t* out_id,
+                           int8_t* out_status, uint32_t* out_sketch, int64_t* out_ids, int32_t* out_dist,
+                           double* out_latency_s, int64_t* n_out)
+{
+    if (!S || !n_out || max_out < 0 || (max_out > 0 && !out_id)) return DMS_EINVAL;
+    *n_out = 0;
+    const dms_server_config& C = S->cfg;
+    if (hipSetDevice(dms::ctx_device(S->ctx)) != hipSuccess) return DMS_EHIP;
+    using clk = std::chrono::steady_clock;
+    const auto until = clk::now() + std::chrono::milliseconds(wait_ms > 0 ? wait_ms : 0);
+    for (;;) {
+        // completions
+        for (Slot& s : S->slots) {
+            if (!s.busy || s.online_id.empty()) continue;
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return DMS_EHIP;
+            const double tc = std::chrono::duration<double>(clk::now() - S->t0).count();
+            std::vector<int64_t> search_row(s.reqs.size(), -1);
+            for (int64_t qi = 0; qi < s.n_q; ++qi) search_row[(size_t)s.query_row[qi]] = qi;
+            for (size_t i = 0; i < s.reqs.size(); ++i) {
+                const int64_t local = s.reqs[i];
+                OnlineDone d;
+                d.id = s.online_id[(size_t)local];
+                d.k = s.online_k[(size_t)local];
+                d.status = s.h_status[i];
+                d.sketch.assign(s.h_u32 + s.out_off[i], s.h_u32 + s.out_off[i] + d.k);
+                if (search_row[i] >= 0) {
+                    const int64_t qi = search_row[i];
+                    d.search = true;
+                    d.ids.assign(s.h_ids + qi * C.topk, s.h_ids + (qi + 1) * C.topk);
+                    d.dist.assign(s.h_dist + qi * C.topk, s.h_dist + (qi + 1) * C.topk);
+                }
+                auto it = S->requests.find(d.id);
+                d.latency = tc - it->second.t_submit;
+                S->requests.erase(it);
+                S->answers.push_back(std::move(d));
+            }
+            S->in_flight -= (int64_t)s.reqs.size();
+            s.online_id.clear();
+            s.online_k.clear();
+            s.busy = false;
+        }
+        // admission into free slots, in submission order, within each slot's memory
+        for (Slot& s : S->slots) {
+            if (s.busy || S->waiting.empty()) continue;
+            std::vector<int32_t> kind_b, k_b, idx_b;
+            std::vector<double> w_b;
+            std::vector<int64_t> rp_b(1, 0), take;
+            int64_t nnz = 0;
+            while (!S->waiting.empty() && (int64_t)take.size() < C.max_batch) {
+                const OnlineReq& r = S->requests.at(S->waiting.front());
+                const int64_t n = (int64_t)r.idx.size();
+                if (nnz + n > C.max_batch_nnz) break;  // waits for the next slot
+                kind_b.push_back(r.kind);
+                k_b.push_back(r.k);
+                idx_b.insert(idx_b.end(), r.idx.begin(), r.idx.end());
+                w_b.insert(w_b.end(), r.w.begin(), r.w.end());
+                nnz += n;
+                rp_b.push_back(nnz);
+                s.online_id.push_back(S->waiting.front());
+                s.online_k.push_back(r.k);
+                take.push_back((int64_t)take.size());
+                S->waiting.pop_front();
+            }
+            const dms_status st = launch_batch(S, s, take, kind_b.data(), k_b.data(), rp_b.data(),
+                                               idx_b.data(), w_b.data());
+            if (st != DMS_OK) {
+                // the batch never ran: its requests go back to the head of the queue
+                for (auto it = s.online_id.rbegin(); it != s.online_id.rend(); ++it) S->waiting.push_front(*it);
+                s.online_id.clear();
+                s.online_k.clear();
+                return st;
+            }
+            S->in_flight += (int64_t)take.size();
+        }
+        if (!S->answers.empty() || S->in_flight == 0 || clk::now() >= until) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    int64_t n = 0;
+    while (n < max_out && !S->answers.empty()) {
+        const OnlineDone& d = S->answers.front();
+        out_id[n] = d.id;
+        if (out_status) out_status[n] = d.status;
+        if (out_sketch) std::memcpy(out_sketch + n * 1024, d.sketch.data(), (size_t)d.k * sizeof(uint32_t));
+        if (d.search) {
+            if (out_ids) std::memcpy(out_ids + n * C.topk, d.ids.data(), (size_t)C.topk * sizeof(int64_t));
+            if (out_dist) std::memcpy(out_dist + n * C.topk, d.dist.data(), (size_t)C.topk * sizeof(int32_t));
+        }
+        if (out_latency_s) out_latency_s[n] = d.latency;
+        S->answers.pop_front();
+        ++n;
+    }
+    *n_out = n;
     return DMS_OK;
 }
 

@@ -23,7 +23,8 @@ FMT_U32, FMT_1BIT = 0, 1
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
            "dms_last_error", "dms_status_str", "dms_t_of_k", "dms_spec_constants", "dms_calibrate",
-           "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_bbit_pack",
+           "dms_server_create", "dms_server_destroy", "dms_server_replay", "dms_server_submit",
+           "dms_server_poll", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
            "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune",
            "dms_spec_tabulation"]
@@ -84,6 +85,8 @@ def lib():
         "dms_server_create": ([vp, P(ServerConfig), vp, i64, P(vp)], i32),
         "dms_server_destroy": ([vp], i32),
         "dms_server_replay": ([vp, i64] + [vp] * 13, i32),
+        "dms_server_submit": ([vp, i32, i32, i64, vp, vp, P(i64)], i32),
+        "dms_server_poll": ([vp, i32, i64] + [vp] * 7, i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -438,6 +441,36 @@ class Server:
         return dict(sketch=sketches, status=status, ids=ids, dist=dist, latency=lat,
                     stats=dict(req_per_s=stats[0], p50_s=stats[1], p99_s=stats[2], max_s=stats[3],
                                batches=int(stats[4]), mean_batch=stats[5], elapsed_s=stats[6]))
+
+    def submit(self, kind, k, idx, w):
+        """Submit one request (host arrays); returns its id."""
+        np = self._np
+        idx = np.ascontiguousarray(idx, np.int32)
+        w = np.ascontiguousarray(w, np.float64)
+        rid = ctypes.c_int64(0)
+        st = lib().dms_server_submit(self._h, int(kind), int(k), len(idx), _ptr(idx), _ptr(w),
+                                     ctypes.byref(rid))
+        if st != DMS_OK:
+            raise DMSError(f"dms_server_submit: {lib().dms_status_str(st).decode()}")
+        return rid.value
+
+    def poll(self, wait_ms=0, max_out=1024):
+        """Answers finished so far: list of dicts (id, status, sketch, and for
+        search requests ids and dist), in completion order."""
+        np = self._np
+        out_id = np.zeros(max_out, np.int64)
+        status = np.zeros(max_out, np.int8)
+        sk = np.zeros((max_out, 1024), np.uint32)
+        ids = np.full((max_out, self.topk), -2, np.int64)
+        dist = np.full((max_out, self.topk), -2, np.int32)
+        lat = np.zeros(max_out, np.float64)
+        n = ctypes.c_int64(0)
+        st = lib().dms_server_poll(self._h, int(wait_ms), max_out, _ptr(out_id), _ptr(status), _ptr(sk),
+                                   _ptr(ids), _ptr(dist), _ptr(lat), ctypes.byref(n))
+        if st != DMS_OK:
+            raise DMSError(f"dms_server_poll: {lib().dms_status_str(st).decode()}")
+        return [dict(id=int(out_id[i]), status=int(status[i]), sketch=sk[i], ids=ids[i], dist=dist[i],
+                     latency=float(lat[i])) for i in range(n.value)]
 
 
 def to_device(row_ptr, idx, w, device="cuda"):

@@ -156,6 +156,80 @@ def test_split_threshold_does_not_change_results(torch, ctx, served, split):
         assert np.array_equal(got["ids"][r], served["out"]["ids"][r])
 
 
+def _serve_online(srv, kind, k, rp, idx, w, burst):
+    # submit in bursts, polling between them, then drain
+    ids, got = [], {}
+    n = len(kind)
+    for b0 in range(0, n, burst):
+        for r in range(b0, min(n, b0 + burst)):
+            ids.append(srv.submit(kind[r], k[r], idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]))
+        for a in srv.poll(wait_ms=0):
+            got[a["id"]] = a
+    for _ in range(2000):
+        if len(got) == n:
+            break
+        for a in srv.poll(wait_ms=20, max_out=64):
+            assert a["id"] not in got
+            got[a["id"]] = a
+    return ids, got
+
+
+@pytest.mark.parametrize("burst,max_batch", [(1, 64), (17, 8), (240, 64)])
+def test_online_submit_poll_equals_replay_and_oracle(torch, ctx, served, burst, max_batch):
+    # requests handed in one by one (dms_server_submit) and collected as they
+    # finish (dms_server_poll) get the answers the trace replay gave, which
+    # equal the oracle's
+    from paper_2005_11547_amd import Server
+    arrival, kind, k, rp, idx, w = served["trace"]
+    srv = Server(ctx, served["db"], topk=10, max_batch=max_batch, max_inflight=3)
+    print(f"[online] burst={burst} max_batch={max_batch}", flush=True)
+    ids, got = _serve_online(srv, kind, k, rp, idx, w, burst)
+    assert ids == list(range(len(kind)))              # ids are handed out in order
+    assert len(got) == len(kind)
+    assert srv.poll(wait_ms=0) == []                   # nothing left over
+    ref = served["out"]
+    for r, rid in enumerate(ids):
+        a = got[rid]
+        assert a["status"] == ref["status"][r]
+        assert np.array_equal(a["sketch"][:k[r]], ref["sketch"][r]), r
+        if kind[r] == 1:
+            assert np.array_equal(a["ids"], ref["ids"][r]) and np.array_equal(a["dist"], ref["dist"][r]), r
+        else:
+            assert (a["ids"] == -2).all()
+        assert a["latency"] > 0
+    for r in range(0, len(kind), 40):                  # a sample straight against the oracle
+        ii, ww = idx[rp[r]:rp[r + 1]], w[rp[r]:rp[r + 1]]
+        o = O.sketch_csr(np.array([0, len(ii)]), ii, ww, int(k[r]), SEED)
+        assert np.array_equal(got[ids[r]]["sketch"][:k[r]], o["u32"][0])
+    srv.close()
+
+
+def test_online_requests_block_a_replay_and_bad_requests_are_refused(torch, ctx, served):
+    from paper_2005_11547_amd import DMSError, Server
+    arrival, kind, k, rp, idx, w = served["trace"]
+    srv = Server(ctx, served["db"], topk=10, max_batch=8, max_inflight=1, max_set_nnz=4096)
+    with pytest.raises(DMSError):
+        srv.submit(1, 64, idx[:3], w[:3])              # a search needs k = 1024
+    with pytest.raises(DMSError):
+        srv.submit(0, 128, idx[:3], w[:3])             # k outside 64, 256, 1024
+    with pytest.raises(DMSError):
+        srv.submit(0, 64, np.zeros(5000, np.int32), np.ones(5000))  # above max_set_nnz
+    rid = srv.submit(0, 64, idx[rp[0]:rp[1]], w[rp[0]:rp[1]])
+    with pytest.raises(DMSError):                      # a replay may not overtake pending requests
+        srv.replay(arrival[:1], kind[:1], k[:1], rp[:2], idx[:rp[1]], w[:rp[1]])
+    got = []
+    for _ in range(500):
+        got += srv.poll(wait_ms=20)
+        if got:
+            break
+    assert [a["id"] for a in got] == [rid]
+    out = srv.replay(arrival[:1] * 0.0, np.zeros(1, np.int32), np.array([64], np.int32), rp[:2],
+                     idx[:rp[1]], w[:rp[1]])
+    assert np.array_equal(out["sketch"][0], got[0]["sketch"][:64])
+    assert out["status"][0] == got[0]["status"]
+    srv.close()
+
+
 def test_closing_a_context_closes_its_server_and_index_first(torch, ctx, served):
     # the C ABI needs servers and indexes destroyed before their context; the
     # binding does it, and no stale HIP error reaches later calls
