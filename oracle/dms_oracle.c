@@ -250,21 +250,36 @@ int dmso_darthash(const dmso_params* P, int64_t nnz, const int32_t* idx, const d
 }
 
 /*
+ * Enumeration counts of a schedule: cnt[0] sums every DartHash pass, cnt[1]
+ * keeps the last pass only (the work of one pass at the final phi).  cnt may
+ * be NULL.
+ */
+static void count_pass(dmso_counters* cnt, const dmso_counters* c)
+{
+    if (!cnt) return;
+    cnt[0].regions += c->regions;
+    cnt[0].areas += c->areas;
+    cnt[0].generated += c->generated;
+    cnt[0].rank_pass += c->rank_pass;
+    cnt[0].accepted += c->accepted;
+    cnt[1] = *c;
+}
+
+/*
  * DartMinHash for one set (Theorem 1): run DartHash_t(x, phi) for phi = phi0,
  * then the schedule's next values, hash every returned dart to one of k
  * buckets by b = (hi32(s) * k) >> 32, stop once no bucket is empty.  Bucket j's
  * minhash is its dart of smallest rank (ties broken by the smaller id hash s).
- * On success writes out_s[j], out_rank[j] for j < k and *phi_final.
+ * On success writes out_s[j], out_rank[j] for j < k and *phi_final.  cnt, if
+ * not NULL, points at two counters: every pass summed, and the last pass.
  */
 int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t* idx,
                      const double* x, uint64_t* out_s, double* out_rank, double* phi_final,
-                     dmso_counters* cnt_total)
+                     dmso_counters* cnt)
 {
     double S;
     int st = check_row(nnz, x, &S);
     if (st != DMSO_OK) return st;
-    dmso_counters tot;
-    memset(&tot, 0, sizeof tot);
     int filled = 0;
     double phi = P->phi0;
     uint8_t* have = (uint8_t*)malloc((size_t)k);
@@ -276,8 +291,7 @@ int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
         dmso_counters c;
         memset(&c, 0, sizeof c);
         st = darthash(P, nnz, idx, x, tau, &L, &c);
-        tot.regions += c.regions; tot.areas += c.areas; tot.generated += c.generated;
-        tot.rank_pass += c.rank_pass; tot.accepted += c.accepted;
+        count_pass(cnt, &c);
         if (st != DMSO_OK) { free(L.d); break; }
         memset(have, 0, (size_t)k);
         for (int64_t n = 0; n < L.n; n++) {
@@ -296,13 +310,13 @@ int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
         phi = next_phi(P, phi);
     }
     free(have);
-    if (cnt_total) *cnt_total = tot;
     return st;
 }
 
 /*
  * Batched DartMinHash over a CSR matrix.  Sets with a non-OK status get
- * minhash 0xFFFFFFFF and all-zero bits.  Any output pointer may be NULL.
+ * minhash 0xFFFFFFFF and all-zero bits.  Any output pointer may be NULL;
+ * out_cnt holds two counters per set (every pass summed, the last pass).
  * out_u32[s*k + j] = low 32 bits of bucket j's dart hash; bit j of set s is
  * bit 0 of that hash, stored at bit (j mod 64) of word s*ceil(k/64) + j/64.
  */
@@ -318,13 +332,13 @@ int dmso_sketch_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr
     for (int64_t q = 0; q < n_sets; q++) {
         int64_t b0 = row_ptr[q], b1 = row_ptr[q + 1];
         double phi = 0.0;
-        dmso_counters c;
-        memset(&c, 0, sizeof c);
-        int st = dmso_minhash_set(P, k, b1 - b0, idx + b0, x + b0, s, rk, &phi, &c);
+        dmso_counters c[2];
+        memset(c, 0, sizeof c);
+        int st = dmso_minhash_set(P, k, b1 - b0, idx + b0, x + b0, s, rk, &phi, c);
         if (st == DMSO_NOMEM) { free(s); free(rk); return DMSO_NOMEM; }
         if (out_status) out_status[q] = (int8_t)st;
         if (out_phi) out_phi[q] = st == DMSO_OK ? phi : 0.0;
-        if (out_cnt) out_cnt[q] = c;
+        if (out_cnt) { out_cnt[2 * q] = c[0]; out_cnt[2 * q + 1] = c[1]; }
         for (int32_t j = 0; j < k; j++) {
             if (out_u32) out_u32[q * k + j] = st == DMSO_OK ? (uint32_t)s[j] : 0xFFFFFFFFu;
             if (out_s) out_s[q * k + j] = st == DMSO_OK ? s[j] : ~0ULL;
@@ -352,7 +366,7 @@ int dmso_sketch_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr
  */
 int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const int32_t* idx,
                  const double* x, uint64_t* out_keys, uint64_t* out_s, double* out_rank,
-                 double* phi_final)
+                 double* phi_final, dmso_counters* pass_cnt)
 {
     double S;
     int st = check_row(nnz, x, &S);
@@ -370,6 +384,7 @@ int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const 
         dmso_counters c;
         memset(&c, 0, sizeof c);
         st = darthash(P, nnz, idx, x, tau, &D, &c);
+        count_pass(pass_cnt, &c);
         if (st != DMSO_OK) { free(D.d); break; }
         for (int32_t l = 0; l < L; l++) cnt[l] = 0;
         for (int64_t n = 0; n < D.n; n++) {
@@ -416,12 +431,15 @@ int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const 
 /* Batched LSH keys over a CSR matrix; non-OK sets get all-zero keys. */
 int dmso_lsh_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr,
                  const int32_t* idx, const double* x, int32_t L, int32_t K,
-                 uint64_t* out_keys, int8_t* out_status)
+                 uint64_t* out_keys, int8_t* out_status, dmso_counters* out_cnt)
 {
     for (int64_t q = 0; q < n_sets; q++) {
         int64_t b0 = row_ptr[q], b1 = row_ptr[q + 1];
         double phi = 0.0;
-        int st = dmso_lsh_set(P, L, K, b1 - b0, idx + b0, x + b0, out_keys + q * L, NULL, NULL, &phi);
+        dmso_counters c[2];
+        memset(c, 0, sizeof c);
+        int st = dmso_lsh_set(P, L, K, b1 - b0, idx + b0, x + b0, out_keys + q * L, NULL, NULL, &phi, c);
+        if (out_cnt) { out_cnt[2 * q] = c[0]; out_cnt[2 * q + 1] = c[1]; }
         if (st == DMSO_NOMEM) return DMSO_NOMEM;
         if (out_status) out_status[q] = (int8_t)st;
         if (st != DMSO_OK)
@@ -448,7 +466,8 @@ static int cmp_dart(const void* pa, const void* pb)
  * element id) counts once.
  */
 int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t* idx,
-                     const double* x, uint64_t* out_s, double* out_rank, double* phi_final)
+                     const double* x, uint64_t* out_s, double* out_rank, double* phi_final,
+                     dmso_counters* cnt)
 {
     double S;
     int st = check_row(nnz, x, &S);
@@ -460,6 +479,7 @@ int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
         dmso_counters c;
         memset(&c, 0, sizeof c);
         st = darthash(P, nnz, idx, x, phi / S, &L, &c);
+        count_pass(cnt, &c);
         if (st != DMSO_OK) { free(L.d); return st; }
         if (L.n > 1) qsort(L.d, (size_t)L.n, sizeof(dmso_dart), cmp_dart);
         int64_t distinct = 0;
@@ -485,12 +505,15 @@ int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
 /* Batched bottom-k sketches; non-OK sets get s = ~0 and rank = +inf. */
 int dmso_bottomk_csr(const dmso_params* P, int64_t n_sets, const int64_t* row_ptr,
                      const int32_t* idx, const double* x, int32_t k, uint64_t* out_s,
-                     double* out_rank, int8_t* out_status)
+                     double* out_rank, int8_t* out_status, dmso_counters* out_cnt)
 {
     for (int64_t q = 0; q < n_sets; q++) {
         int64_t b0 = row_ptr[q], b1 = row_ptr[q + 1];
         double phi = 0.0;
-        int st = dmso_bottomk_set(P, k, b1 - b0, idx + b0, x + b0, out_s + q * k, out_rank + q * k, &phi);
+        dmso_counters c[2];
+        memset(c, 0, sizeof c);
+        int st = dmso_bottomk_set(P, k, b1 - b0, idx + b0, x + b0, out_s + q * k, out_rank + q * k, &phi, c);
+        if (out_cnt) { out_cnt[2 * q] = c[0]; out_cnt[2 * q + 1] = c[1]; }
         if (st == DMSO_NOMEM) return DMSO_NOMEM;
         if (out_status) out_status[q] = (int8_t)st;
         if (st != DMSO_OK)

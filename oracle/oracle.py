@@ -189,11 +189,12 @@ def lib():
         L.dmso_sketch_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32,
                                       vp, vp, vp, vp, vp, vp, vp]
         L.dmso_lsh_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                   vp, vp, vp, vp, vp, P(ctypes.c_double)]
+                                   vp, vp, vp, vp, vp, P(ctypes.c_double), vp]
         L.dmso_lsh_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32,
-                                   ctypes.c_int32, vp, vp]
-        L.dmso_bottomk_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, vp]
-        L.dmso_bottomk_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+                                   ctypes.c_int32, vp, vp, vp]
+        L.dmso_bottomk_set.argtypes = [P(Params), ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+        L.dmso_bottomk_csr.argtypes = [P(Params), ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
+                                       vp]
         for f in ("dmso_bottomk_set", "dmso_bottomk_csr"):
             getattr(L, f).restype = ctypes.c_int
         for f in ("dmso_darthash", "dmso_minhash_set", "dmso_sketch_csr", "dmso_lsh_set",
@@ -277,10 +278,10 @@ def minhash_set(idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1
     s = np.zeros(k, dtype=np.uint64)
     r = np.zeros(k, dtype=np.float64)
     phi = ctypes.c_double(0.0)
-    cnt = Counters()
+    cnt = (Counters * 2)()
     st = lib().dmso_minhash_set(ctypes.byref(P), k, len(idx), _ptr(idx), _ptr(w), _ptr(s),
-                                _ptr(r), ctypes.byref(phi), ctypes.byref(cnt))
-    return st, s, r, phi.value, {f: getattr(cnt, f) for f, _ in Counters._fields_}
+                                _ptr(r), ctypes.byref(phi), cnt)
+    return st, s, r, phi.value, {f: getattr(cnt[0], f) for f, _ in Counters._fields_}
 
 
 def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
@@ -288,7 +289,8 @@ def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: f
     """DartMinHash of every row of a CSR matrix.
 
     Returns dict with u32 [n,k], bits [n, ceil(k/64)] (uint64), status [n] (int8),
-    and with ``full`` also s [n,k], rank [n,k], phi [n], counters [n]."""
+    and with ``full`` also s [n,k], rank [n,k], phi [n], counters [n] (every pass
+    summed) and counters_last [n] (the last pass)."""
     t = t_of_k(k) if t is None else t
     P = make_params(seed, t, phi0, schedule, hash=hash)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
@@ -300,7 +302,7 @@ def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: f
     s = np.zeros((n, k), dtype=np.uint64) if full else None
     rk = np.zeros((n, k), dtype=np.float64) if full else None
     phi = np.zeros(n, dtype=np.float64) if full else None
-    cnt = np.zeros(n, dtype=COUNTER_DTYPE) if full else None
+    cnt = np.zeros((n, 2), dtype=COUNTER_DTYPE) if full else None
     st = lib().dmso_sketch_csr(ctypes.byref(P), n, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
                                _ptr(u32), _ptr(bits), _ptr(status), _ptr(s), _ptr(rk),
                                _ptr(phi), _ptr(cnt))
@@ -308,7 +310,7 @@ def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: f
         raise MemoryError("oracle out of memory")
     out = dict(u32=u32, bits=bits, status=status)
     if full:
-        out.update(s=s, rank=rk, phi=phi, counters=cnt)
+        out.update(s=s, rank=rk, phi=phi, counters=cnt[:, 0].copy(), counters_last=cnt[:, 1].copy())
     return out
 
 
@@ -323,22 +325,28 @@ def lsh_set(idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
     r = np.zeros((L, K), dtype=np.float64)
     phi = ctypes.c_double(0.0)
     st = lib().dmso_lsh_set(ctypes.byref(P), L, K, len(idx), _ptr(idx), _ptr(w), _ptr(keys),
-                            _ptr(s), _ptr(r), ctypes.byref(phi))
+                            _ptr(s), _ptr(r), ctypes.byref(phi), None)
     return st, keys, s, r, phi.value
 
 
 def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
-            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
+            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False):
+    """(L,K) LSH keys of every row: dict keys [n,L] uint64, status [n] int8, and
+    with ``counters`` the enumeration counts [n,2] (every pass summed, last pass)."""
     P = make_params(seed, L * K, phi0, schedule, hash=hash)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
     n = len(row_ptr) - 1
     keys = np.zeros((n, L), dtype=np.uint64)
     status = np.zeros(n, dtype=np.int8)
+    cnt = np.zeros((n, 2), dtype=COUNTER_DTYPE) if counters else None
     st = lib().dmso_lsh_csr(ctypes.byref(P), n, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
-                            _ptr(keys), _ptr(status))
+                            _ptr(keys), _ptr(status), _ptr(cnt))
     if st != 0:
         raise MemoryError("oracle out of memory")
-    return dict(keys=keys, status=status)
+    out = dict(keys=keys, status=status)
+    if counters:
+        out["counters"] = cnt
+    return out
 
 
 def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE,
@@ -352,25 +360,30 @@ def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SC
     r = np.zeros(k, dtype=np.float64)
     phi = ctypes.c_double(0.0)
     st = lib().dmso_bottomk_set(ctypes.byref(P), k, len(idx), _ptr(idx), _ptr(w), _ptr(s), _ptr(r),
-                                ctypes.byref(phi))
+                                ctypes.byref(phi), None)
     return st, s, r, phi.value
 
 
 def bottomk_csr(row_ptr, idx, w, k: int, seed: int, phi0: float = 1.0,
-                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX):
+                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False):
     """Bottom-k sketches of every row: dict s [n,k] uint64, rank [n,k] float64,
-    u32 [n,k] (low 32 bits of s), status [n] int8."""
+    u32 [n,k] (low 32 bits of s), status [n] int8, and with ``counters`` the
+    enumeration counts [n,2] (every pass summed, last pass)."""
     rp, idx, w = _csr(row_ptr, idx, w)
     n = len(rp) - 1
     P = make_params(seed, k, phi0, schedule, hash=hash)
     s = np.zeros((n, k), dtype=np.uint64)
     r = np.zeros((n, k), dtype=np.float64)
     st = np.zeros(n, dtype=np.int8)
+    cnt = np.zeros((n, 2), dtype=COUNTER_DTYPE) if counters else None
     rc = lib().dmso_bottomk_csr(ctypes.byref(P), n, _ptr(rp), _ptr(idx), _ptr(w), k, _ptr(s), _ptr(r),
-                                _ptr(st))
+                                _ptr(st), _ptr(cnt))
     if rc != 0:
         raise MemoryError("dmso_bottomk_csr")
-    return {"s": s, "rank": r, "u32": (s & np.uint64(0xFFFFFFFF)).astype(np.uint32), "status": st}
+    out = {"s": s, "rank": r, "u32": (s & np.uint64(0xFFFFFFFF)).astype(np.uint32), "status": st}
+    if counters:
+        out["counters"] = cnt
+    return out
 
 
 def jaccard_est_bottomk(rank_a, s_a, rank_b, s_b):
