@@ -171,73 +171,31 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
 }
 
 // (L,K) LSH tables of one wave: table l holds cnt[l] <= K darts sorted by
-// (rank, id hash).  insert_one and insert_row8 are run by one lane per table
-// at a time; ticket[l] is the table's ticket counter.
+// (rank, id hash); ticket[l] is the table's ticket counter.
 struct LshTables {
     uint64_t* rank;
     uint64_t* sval;
     uint8_t* cnt;
     int32_t* ticket;
+    // staging of the darts of one ticket: the accept round's consumed
+    // pass-queue slots (rank bits, id hash, table), which it no longer reads
+    uint64_t* stage_r;
+    uint64_t* stage_s;
+    uint32_t* stage_l;
     int K;
 
-    __device__ void insert_one(uint32_t l, uint64_t rb, uint64_t s) const
-    {
-        uint64_t* r = rank + (size_t)l * K;
-        uint64_t* v = sval + (size_t)l * K;
-        const int c = cnt[l];
-        int pos = 0;
-        for (int m = 0; m < c; ++m) {
-            if (r[m] == rb && v[m] == s) return;  // the same dart again (repeated element id)
-            pos += (r[m] < rb || (r[m] == rb && v[m] < s)) ? 1 : 0;
-        }
-        if (pos >= K) return;
-        for (int m = (c < K ? c : K - 1); m > pos; --m) {
-            r[m] = r[m - 1];
-            v[m] = v[m - 1];
-        }
-        r[pos] = rb;
-        v[pos] = s;
-        if (c < K) cnt[l] = c + 1;
-    }
-
-    // K = 8: the row's eight entries are read at once (independent loads), the
-    // position is found in registers and the whole row is rewritten.  Entries
-    // past the count are never taken for darts.
-    __device__ void insert_row8(uint32_t l, uint64_t rb, uint64_t s) const
-    {
-        uint64_t* r = rank + (size_t)l * 8;
-        uint64_t* v = sval + (size_t)l * 8;
-        const int c = cnt[l];
-        uint64_t R[8], V[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            R[m] = r[m];
-            V[m] = v[m];
-        }
-        int pos = 0;
-        bool dup = false;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const bool in = m < c;
-            dup |= in && R[m] == rb && V[m] == s;  // the same dart again (repeated element id)
-            pos += (in && (R[m] < rb || (R[m] == rb && V[m] < s))) ? 1 : 0;
-        }
-        if (dup || pos >= 8) return;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            r[m] = m < pos ? R[m] : m == pos ? rb : R[m > 0 ? m - 1 : 0];
-            v[m] = m < pos ? V[m] : m == pos ? s : V[m > 0 ? m - 1 : 0];
-        }
-        if (c < 8) cnt[l] = (uint8_t)(c + 1);
-    }
-
-    // Called by all 64 lanes; lanes with `has` insert their dart.  A dart above
-    // a full table's largest is dropped at once (later insertions only lower
-    // that bound).  The others draw tickets from their table's counter; step i
-    // inserts the darts holding ticket i, at most one per table, so different
-    // tables fill in parallel and no table is written twice in a step.  The
-    // order of insertions does not change a table's final K smallest darts.
-    __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s) const
+    // Called by all 64 lanes of an accept round whose pass-queue head is
+    // `head`; lanes with `has` insert their dart into table l.  A dart above a
+    // full table's largest is dropped at once (later insertions only lower that
+    // bound).  The others draw tickets from their table's counter, and the
+    // darts holding ticket i (at most one per table) are inserted together by
+    // groups of G >= K lanes, one dart per group: lane j of a group holds entry
+    // j of the dart's table, the group counts the entries below the dart, and
+    // the entries from that position on move up by one.  Tickets are taken in
+    // ascending order, so a table is written by one group at a time.  The order
+    // of insertions does not change a table's final K smallest darts; a dart
+    // equal to an entry (a repeated element id) is dropped.
+    __device__ void insert(bool has, uint32_t l, uint64_t rb, uint64_t s, uint32_t head, int lane) const
     {
         bool pending = has;
         if (pending && cnt[l] >= K) {
@@ -246,17 +204,60 @@ struct LshTables {
         }
         if (!wave_any(pending)) return;
         if (pending) __hip_atomic_store(&ticket[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        wave_sync();
+        wave_sync();  // also: every lane has read its pass-queue entry
         int mine = 0;
         if (pending)
             mine = __hip_atomic_fetch_add(&ticket[l], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        for (int step = 0; wave_any(pending); ++step) {
-            if (pending && mine == step) {
-                if (K == 8) insert_row8(l, rb, s);
-                else insert_one(l, rb, s);
+        const uint32_t gsh = K <= 1 ? 0u : 32u - (uint32_t)__clz(K - 1);  // G = 2^gsh
+        const uint32_t j = (uint32_t)lane & ((1u << gsh) - 1u);
+        const uint32_t g = (uint32_t)lane >> gsh;
+        const uint32_t groups = 64u >> gsh;
+        const uint64_t gmask = gsh == 6 ? ~0ull : (1ull << (1u << gsh)) - 1ull;
+        const uint32_t uK = (uint32_t)K;
+        for (int level = 0; wave_any(pending); ++level) {
+            const bool here = pending && mine == level;
+            const uint64_t b = __ballot(here);
+            const uint32_t n = (uint32_t)__popcll(b);
+            if (here) {
+                const uint32_t q = ring_p(head + rank_in(b));
+                stage_r[q] = rb;
+                stage_s[q] = s;
+                stage_l[q] = l;
                 pending = false;
             }
             wave_sync();
+            for (uint32_t base = 0; base < n; base += groups) {
+                const uint32_t q = base + g;
+                const bool act = q < n;
+                uint32_t tl = 0;
+                uint64_t dr = 0, dsv = 0;
+                if (act) {
+                    const uint32_t p = ring_p(head + q);
+                    tl = stage_l[p];
+                    dr = stage_r[p];
+                    dsv = stage_s[p];
+                }
+                const uint32_t c = act ? (uint32_t)cnt[tl] : 0u;
+                const bool in = j < c;
+                uint64_t R = 0, V = 0;
+                if (in) {
+                    R = rank[(size_t)tl * K + j];
+                    V = sval[(size_t)tl * K + j];
+                }
+                const uint64_t bl = __ballot(in && (R < dr || (R == dr && V < dsv)));
+                const uint64_t bd = __ballot(in && R == dr && V == dsv);
+                const uint32_t pos = (uint32_t)__popcll((bl >> (g << gsh)) & gmask);
+                const bool dup = ((bd >> (g << gsh)) & gmask) != 0;
+                // entry j - 1 of the same group (lane - 1); used only when j > pos >= 0
+                const uint64_t Rp = __shfl(R, lane - 1, kWave), Vp = __shfl(V, lane - 1, kWave);
+                const bool put = act && !dup && pos < uK;
+                if (put && j < uK && j >= pos && j <= c) {
+                    rank[(size_t)tl * K + j] = j == pos ? dr : Rp;
+                    sval[(size_t)tl * K + j] = j == pos ? dsv : Vp;
+                }
+                if (put && j == 0 && c < uK) cnt[tl] = (uint8_t)(c + 1);
+            }
+            wave_sync();  // the next ticket may use the same tables and staging slots
         }
     }
 };
@@ -327,6 +328,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     T.cnt = reinterpret_cast<uint8_t*>(bin_s + k * K);
     T.ticket = k <= kWave ? &at<int32_t>(wb, kOffMark, 0)
                          : reinterpret_cast<int32_t*>(T.cnt + ((k + 7) / 8) * 8);
+    T.stage_r = &at<uint64_t>(wb, kOffPqRank, 0);
+    T.stage_s = &at<uint64_t>(wb, kOffPqA, 0);
+    T.stage_l = &at<uint32_t>(wb, kOffPqE, 0);
     T.K = K;
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
@@ -527,7 +531,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         uint64_t s = 0;
                         if (acc) s = H(a ^ KS ^ j);
                         if (LSH) {
-                            T.insert(acc, bucket_of(s, (uint32_t)k), rb, s);
+                            T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, pq_head, lane);
                         } else if (BK) {
                             bool keep = acc && (rb < cut_r || (rb == cut_r && s < cut_s));
                             uint64_t bk = __ballot(keep);

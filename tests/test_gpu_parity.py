@@ -142,6 +142,22 @@ def test_lsh_more_than_64_tables(torch, ctx):
         assert np.array_equal(out["keys"].cpu().numpy().view(np.uint64), ref["keys"]), (L, K)
 
 
+def test_lsh_wide_tables(torch, ctx):
+    # darts enter a table through a group of lanes as wide as K rounded up to a
+    # power of two: up to one group of all 64 lanes at K = 64
+    rp, idx, w = WL.lsh_L64K8(seed=92, n_sets=200)
+    rows = [(idx[rp[q]:rp[q + 1]], w[rp[q]:rp[q + 1]]) for q in range(len(rp) - 1)]
+    rows += [([], []), ([4, 4, 9], [0.3, 0.7, 1.0]), ([1], [3.0]), ([7] * 3, [1.0, 2.0, 0.5])]
+    rp, idx, w = WL.csr_from_rows(rows)
+    for L, K in ((2, 64), (3, 33), (4, 32), (8, 20), (16, 9), (24, 16)):
+        print(f"[parity] lsh L={L} K={K}", flush=True)
+        out = ctx.lsh(*_dev(torch, rp, idx, w), L, K)
+        torch.cuda.synchronize()
+        ref = O.lsh_csr(rp, idx, w, L, K, SEED)
+        assert np.array_equal(out["status"].cpu().numpy(), ref["status"]), (L, K)
+        assert np.array_equal(out["keys"].cpu().numpy().view(np.uint64), ref["keys"]), (L, K)
+
+
 def test_jaccard_estimates(torch, ctx):
     from paper_2005_11547_amd import dms
     rng = np.random.default_rng(3)
