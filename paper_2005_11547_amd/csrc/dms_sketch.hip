@@ -128,7 +128,7 @@ constexpr uint32_t kOffRqM = kOffRqFirst + 4 * kCapR;        // u32[kCapR] nu | 
 constexpr uint32_t kOffDqE = kOffRqM + 4 * kCapR;            // u32[kCapD]
 constexpr uint32_t kOffDqR = kOffDqE + 4 * kCapD;            // u32[kCapD]
 constexpr uint32_t kOffDqW = kOffDqR + 4 * kCapD;            // u32[kCapD]
-constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<10|j<<20|X<<25
+constexpr uint32_t kOffDqM = kOffDqW + 4 * kCapD;            // u32[kCapD] nu|rho<<10|j<<20
 constexpr uint32_t kOffPqE = kOffDqM + 4 * kCapD;            // u32[kCapP]
 constexpr uint32_t kOffPqW = kOffPqE + 4 * kCapP;            // u32[kCapP]
 constexpr uint32_t kOffPqM = kOffPqW + 4 * kCapP;            // u32[kCapP] nu|rho<<10|j<<20
@@ -298,11 +298,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 {
     constexpr bool LSH = MODE == kModeLsh;
     constexpr bool BK = MODE == kModeBottomK;
-    // Region and area rounds only need to know whether an area holds one dart
-    // or more than one; with kLazyX the exact Poisson count is drawn (from the
-    // same area hash) by the dart round, which sees only areas with two or more
-    // darts.  Measured faster for minhash and bottom-k, slower for LSH keys.
-    constexpr bool kLazyX = !LSH;
+    // Region and area rounds only need to know whether an area holds no dart,
+    // one, or more (poisson_head); the exact Poisson count is drawn from the
+    // same area hash by the dart round, which sees only areas with two or more.
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
     double* sR = sW + kTable;
@@ -505,7 +503,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         at<uint32_t>(wb, kOffDqE, pos) = ei;
                         at<uint32_t>(wb, kOffDqR, pos) = rv;
                         at<uint32_t>(wb, kOffDqW, pos) = wv;
-                        at<uint32_t>(wb, kOffDqM, pos) = meta | (kLazyX ? 0u : X << 25) | (1u << 20);
+                        at<uint32_t>(wb, kOffDqM, pos) = meta | (1u << 20);
                     }
                     pq_count = uni(pq_count + (uint32_t)__popcll(bp));
                     dq_count = uni(dq_count + (uint32_t)__popcll(bm));
@@ -563,7 +561,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const uint32_t j = (meta >> 20) & 31;
-                        const uint32_t X = kLazyX ? poisson_fast(C, sPois, a) : meta >> 25;
+                        const uint32_t X = poisson_fast(C, sPois, a);
                         const double U = unit53(H(a ^ KU ^ (uint64_t)j));
                         const double rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                         const bool pass = act && rank <= tau && rank > tau_prev;
@@ -577,7 +575,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             at<uint32_t>(wb, kOffPqE, pos) = ei;
                             at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
                             at<uint32_t>(wb, kOffPqW, pos) = wv;
-                            at<uint32_t>(wb, kOffPqM, pos) = meta & ((1u << 25) - 1);
+                            at<uint32_t>(wb, kOffPqM, pos) = meta;
                         }
                         const uint32_t dq_left = dq_count - m;
                         if (more) {
@@ -638,7 +636,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rv = local - wv * rc;
                             }
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                            X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
+                            X = poisson_head(C, a);
                         }
                         emit_area(act, a, ei, rv, wv, meta, X, false);
                         // advance the region queue by m areas
@@ -684,7 +682,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                     nau = rcu;
                                 }
                                 a = H(g ^ KA);
-                                X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
+                                X = poisson_head(C, a);
                                 rest = nau - 1;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, true);
@@ -725,7 +723,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 }
                                 // the region's first area (w = 0, r = 0)
                                 a = H(g ^ KA);
-                                X = kLazyX ? poisson_head(C, a) : poisson_fast(C, sPois, a);
+                                X = poisson_head(C, a);
                                 rest = nau - 1;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, false);
