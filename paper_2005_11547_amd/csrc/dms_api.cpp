@@ -389,7 +389,7 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         const uint32_t* order = nullptr;
         if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
         e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
-                                 c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::kModeLsh, L, K),
+                                 c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::lsh_fast_mode(L, K), L, K),
                                  order, c->hash, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");

@@ -41,7 +41,9 @@ double corner_w(const SpecTables& sp, int nu);
 double corner_r(const SpecTables& sp, int rho);
 
 // Sinks of the fast kernel: k bucket minima, (L,K) LSH tables, bottom-k buffer.
-enum FastMode : int { kModeMinhash = 0, kModeLsh = 1, kModeBottomK = 2 };
+// kModeLshReg: (L,K) LSH with L <= 64 and K = 8, lane l holding table l in
+// registers; kModeLsh keeps the tables in LDS for every other shape.
+enum FastMode : int { kModeMinhash = 0, kModeLsh = 1, kModeBottomK = 2, kModeLshReg = 3 };
 
 // A set with more nonzeros than the split threshold is cut into parts of at
 // most `split` consecutive nonzeros.  Every part runs one phi pass over its

@@ -27,6 +27,8 @@ int fast_waves(int mode, int k, int K);
 int fast_blocks_per_cu(int mode, int k, int K, int waves);
 size_t fast_lds(int mode, int k, int K, int waves);
 const void* fast_kernel_address(int mode, int hash);
+// The fast engine's LSH variant for L tables of K darts (kModeLshReg or kModeLsh).
+int lsh_fast_mode(int L, int K);
 hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,

@@ -156,12 +156,17 @@ __host__ __device__ constexpr size_t lsh_aux_bytes(int L)
     return (size_t)((L + 7) / 8) * 8 + (L > 64 ? (size_t)4 * L : 0);
 }
 
+// Register-table LSH: a mailbox per table (rank bits, id hash, full flag)
+// through which a dart reaches the lane that holds its table.
+constexpr uint32_t kMailboxBytes = 64 * (8 + 8 + 4);
+
 // Bytes of the result area after the queues: k bucket minima (minhash), L
-// sorted lists of K darts plus their bookkeeping (LSH), or the dart buffer
-// (bottom-k).
+// sorted lists of K darts plus their bookkeeping (LSH), a mailbox per table
+// (register-table LSH), or the dart buffer (bottom-k).
 __host__ __device__ constexpr size_t sink_bytes(int mode, int k, int K)
 {
-    return mode == kModeLsh ? (size_t)16 * k * K + lsh_aux_bytes(k)
+    return mode == kModeLshReg ? (size_t)kMailboxBytes
+         : mode == kModeLsh ? (size_t)16 * k * K + lsh_aux_bytes(k)
          : mode == kModeBottomK ? (size_t)16 * bk_cap(k)
                                 : (size_t)16 * k;
 }
@@ -296,7 +301,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             unsigned long long* next_set, const Part* __restrict__ parts, int64_t n_parts,
             HeavySet* heavy, uint64_t* partial, int64_t split, const uint32_t* __restrict__ order)
 {
-    constexpr bool LSH = MODE == kModeLsh;
+    constexpr bool RT = MODE == kModeLshReg;  // K = 8 tables in registers, one per lane
+    constexpr bool LSH = MODE == kModeLsh || RT;
     constexpr bool BK = MODE == kModeBottomK;
     // Region and area rounds only need to know whether an area holds no dart,
     // one, or more (poisson_head); the exact Poisson count is drawn from the
@@ -330,6 +336,51 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     T.stage_s = &at<uint64_t>(wb, kOffPqA, 0);
     T.stage_l = &at<uint32_t>(wb, kOffPqE, 0);
     T.K = K;
+    // Register tables: lane l holds table l (l < L), tc darts sorted by (rank
+    // bits, id hash) in tr/ts.  A dart reaches its table's lane through the
+    // table's mailbox (mb_r, mb_s, and mb_f = 1 while it is full).
+    uint64_t tr[8], ts[8];
+    uint32_t tc = 0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        tr[m] = 0;
+        ts[m] = 0;
+    }
+    uint64_t* const mb_r = reinterpret_cast<uint64_t*>(wb + kOffBins);
+    uint64_t* const mb_s = mb_r + 64;
+    uint32_t* const mb_f = reinterpret_cast<uint32_t*>(mb_s + 64);
+    if (RT) {
+        mb_f[lane] = 0;
+        wave_sync();
+    }
+    // Inserts (r, v) into this lane's table unless it is already there.
+    auto reg_insert = [&](uint64_t r, uint64_t v) {
+        bool dup = false;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const bool in = (uint32_t)m < tc;
+            dup |= in && tr[m] == r && ts[m] == v;
+            pos += (in && (tr[m] < r || (tr[m] == r && ts[m] < v))) ? 1u : 0u;
+        }
+        if (!dup && pos < 8) {
+#pragma unroll
+            for (int m = 7; m >= 1; --m) {
+                if ((uint32_t)m > pos) {
+                    tr[m] = tr[m - 1];
+                    ts[m] = ts[m - 1];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                if ((uint32_t)m == pos) {
+                    tr[m] = r;
+                    ts[m] = v;
+                }
+            }
+            if (tc < 8) ++tc;
+        }
+    };
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
     const Hasher<HK> H(sp);
@@ -528,7 +579,41 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         uint64_t s = 0;
                         if (acc) s = H(a ^ KS ^ j);
-                        if (LSH) {
+                        if (RT) {
+                            // a dart above its full table's largest is dropped at once;
+                            // the others go to their table's lane through its mailbox,
+                            // one dart per table at a time (tickets in ascending order)
+                            const uint32_t l = bucket_of(s, (uint32_t)k);
+                            const int src = acc ? (int)l : lane;
+                            const uint32_t oc = (uint32_t)__shfl((int)tc, src, kWave);
+                            const uint64_t omr = __shfl(tr[7], src, kWave), oms = __shfl(ts[7], src, kWave);
+                            bool pending = acc && (oc < 8 || rb < omr || (rb == omr && s <= oms));
+                            if (wave_any(pending)) {
+                                int32_t* const ticket = &at<int32_t>(wb, kOffMark, 0);
+                                if (pending)
+                                    __hip_atomic_store(&ticket[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                wave_sync();
+                                int mine = 0;
+                                if (pending)
+                                    mine = __hip_atomic_fetch_add(&ticket[l], 1, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+                                for (int level = 0; wave_any(pending); ++level) {
+                                    if (pending && mine == level) {
+                                        mb_r[l] = rb;
+                                        mb_s[l] = s;
+                                        mb_f[l] = 1;
+                                        pending = false;
+                                    }
+                                    wave_sync();
+                                    if (mb_f[lane]) {
+                                        const uint64_t r2 = mb_r[lane], v2 = mb_s[lane];
+                                        mb_f[lane] = 0;
+                                        reg_insert(r2, v2);
+                                    }
+                                    wave_sync();
+                                }
+                            }
+                        } else if (LSH) {
                             T.insert(acc, bucket_of(s, (uint32_t)k), rb, s, pq_head, lane);
                         } else if (BK) {
                             bool keep = acc && (rb < cut_r || (rb == cut_r && s < cut_s));
@@ -764,7 +849,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     continue;
                 }
                 bool filled = true;
-                if (LSH) {
+                if (RT) {
+                    filled = lane >= k || tc >= 8u;
+                } else if (LSH) {
                     for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
                 } else {
                     for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
@@ -781,6 +868,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             bk_count = 0;
             cut_r = ~0ull;
             cut_s = ~0ull;
+        } else if (RT) {
+            tc = 0;
         } else if (LSH) {
             for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
         } else {
@@ -860,7 +949,18 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         // outputs
         wave_sync();
         const bool ok = status == kSetOk;
-        if (LSH) {
+        if (RT) {
+            // table l's key folds its 8 ordered dart ids
+            if (lane < k) {
+                uint64_t h = 0;
+                if (ok) {
+                    h = H(sp->key_l ^ (uint64_t)lane);
+#pragma unroll
+                    for (int m2 = 0; m2 < 8; ++m2) h = H(h ^ ts[m2]);
+                }
+                out_keys[set * k + lane] = h;
+            }
+        } else if (LSH) {
             // table l's key folds its K ordered dart ids
             for (int l = lane; l < k; l += kWave) {
                 uint64_t h = 0;
@@ -908,6 +1008,8 @@ DMS_FAST_KERNEL(kModeBottomK, kHashMix)
 DMS_FAST_KERNEL(kModeMinhash, kHashTab)
 DMS_FAST_KERNEL(kModeLsh, kHashTab)
 DMS_FAST_KERNEL(kModeBottomK, kHashTab)
+DMS_FAST_KERNEL(kModeLshReg, kHashMix)
+DMS_FAST_KERNEL(kModeLshReg, kHashTab)
 #undef DMS_FAST_KERNEL
 
 // Planning.  plan[0] = heavy sets, plan[1] = parts (counting pass); plan[2],
@@ -1044,8 +1146,13 @@ int fast_waves(int mode, int k, int K)
 int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, 1); }
 size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, 1, waves); }
 
+int lsh_fast_mode(int L, int K) { return L <= kWave && K == 8 ? kModeLshReg : kModeLsh; }
+
 const void* fast_kernel_address(int mode, int hash)
 {
+    if (mode == kModeLshReg)
+        return hash == kHashTab ? reinterpret_cast<const void*>(&fast_kernel<kModeLshReg, kHashTab>)
+                                : reinterpret_cast<const void*>(&fast_kernel<kModeLshReg, kHashMix>);
     if (hash == kHashTab)
         return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh, kHashTab>)
              : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK, kHashTab>)
@@ -1095,12 +1202,15 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
                            hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves(kModeLsh, L, K);
-    const size_t lds = fast_lds(kModeLsh, L, K, waves);
+    const int mode = lsh_fast_mode(L, K);
+    const int waves = fast_waves(mode, L, K);
+    const size_t lds = fast_lds(mode, L, K, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    auto kern = hash == kHashTab ? fast_kernel<kModeLsh, kHashTab> : fast_kernel<kModeLsh, kHashMix>;
+    auto kern = mode == kModeLshReg ? (hash == kHashTab ? fast_kernel<kModeLshReg, kHashTab>
+                                                        : fast_kernel<kModeLshReg, kHashMix>)
+              : (hash == kHashTab ? fast_kernel<kModeLsh, kHashTab> : fast_kernel<kModeLsh, kHashMix>);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,

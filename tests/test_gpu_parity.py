@@ -149,7 +149,8 @@ def test_lsh_wide_tables(torch, ctx):
     rows = [(idx[rp[q]:rp[q + 1]], w[rp[q]:rp[q + 1]]) for q in range(len(rp) - 1)]
     rows += [([], []), ([4, 4, 9], [0.3, 0.7, 1.0]), ([1], [3.0]), ([7] * 3, [1.0, 2.0, 0.5])]
     rp, idx, w = WL.csr_from_rows(rows)
-    for L, K in ((2, 64), (3, 33), (4, 32), (8, 20), (16, 9), (24, 16)):
+    # K = 8 with L <= 64 keeps each table in one lane's registers
+    for L, K in ((2, 64), (3, 33), (4, 32), (8, 20), (16, 9), (24, 16), (1, 8), (37, 8), (64, 8), (65, 8)):
         print(f"[parity] lsh L={L} K={K}", flush=True)
         out = ctx.lsh(*_dev(torch, rp, idx, w), L, K)
         torch.cuda.synchronize()
