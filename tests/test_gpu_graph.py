@@ -26,14 +26,15 @@ def batch(torch):
     return len(rp) - 1, to_device(rp, idx, w)
 
 
-@pytest.mark.parametrize("order", [1, 0])
-def test_captured_calls_replay_like_eager(torch, batch, order):
+@pytest.mark.parametrize("order,L,K", [(1, 16, 4), (0, 16, 4), (1, 64, 8)])
+def test_captured_calls_replay_like_eager(torch, batch, order, L, K):
+    # (64,8) LSH keeps its tables in registers, (16,4) in LDS
     from paper_2005_11547_amd import Context, dms
     n, d = batch
     c = Context(SEED)
     c.set_option(dms.OPT_SPLIT_NNZ, 0)
     c.set_option(dms.OPT_ORDER, order)
-    k, L, K, kb = 256, 16, 4, 64
+    k, kb = 256, 64
     words = (k + 63) // 64
     u32 = torch.empty((n, k), dtype=torch.int32, device="cuda")
     bits = torch.empty((n, words), dtype=torch.int64, device="cuda")
@@ -50,7 +51,7 @@ def test_captured_calls_replay_like_eager(torch, batch, order):
         c.dms_lsh_keys(n, *d, L, K, keys, lst)
         c.dms_bottomk(n, *d, kb, bs, br, bst)
 
-    print(f"[graph] eager order={order}", flush=True)
+    print(f"[graph] eager order={order} L={L} K={K}", flush=True)
     calls()  # sizes the tables and scratch outside the capture
     torch.cuda.synchronize()
     ref = [t.cpu().clone() for t in outs]
