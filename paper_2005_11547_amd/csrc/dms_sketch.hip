@@ -336,14 +336,16 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     T.stage_s = &at<uint64_t>(wb, kOffPqA, 0);
     T.stage_l = &at<uint32_t>(wb, kOffPqE, 0);
     T.K = K;
-    // Register tables: lane l holds table l (l < L), tc darts sorted by (rank
-    // bits, id hash) in tr/ts.  A dart reaches its table's lane through the
-    // table's mailbox (mb_r, mb_s, and mb_f = 1 while it is full).
+    // Register tables: lane l holds table l (l < L), its darts sorted by (rank
+    // bits, id hash) in tr/ts; unused entries hold rank bits ~0, above every
+    // rank (ranks are finite), so the table is full once tr[7] != ~0.  A dart
+    // reaches its table's lane through the table's mailbox (mb_r, mb_s, and
+    // mb_f = 1 while it holds a dart).
+    constexpr uint64_t kNoRank = ~0ull;
     uint64_t tr[8], ts[8];
-    uint32_t tc = 0;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-        tr[m] = 0;
+        tr[m] = kNoRank;
         ts[m] = 0;
     }
     uint64_t* const mb_r = reinterpret_cast<uint64_t*>(wb + kOffBins);
@@ -353,15 +355,25 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         mb_f[lane] = 0;
         wave_sync();
     }
-    // Inserts (r, v) into this lane's table unless it is already there.
+    // Inserts (r, v) into this lane's table unless it is already there.  The
+    // position is counted on the rank bits alone; only a lane whose rank equals
+    // an entry's recounts with the id hash (and may find the same dart).
     auto reg_insert = [&](uint64_t r, uint64_t v) {
-        bool dup = false;
         uint32_t pos = 0;
+        bool tie = false;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const bool in = (uint32_t)m < tc;
-            dup |= in && tr[m] == r && ts[m] == v;
-            pos += (in && (tr[m] < r || (tr[m] == r && ts[m] < v))) ? 1u : 0u;
+            pos += tr[m] < r ? 1u : 0u;
+            tie |= tr[m] == r;
+        }
+        bool dup = false;
+        if (tie) {
+            pos = 0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                dup |= tr[m] == r && ts[m] == v;
+                pos += (tr[m] < r || (tr[m] == r && ts[m] < v)) ? 1u : 0u;
+            }
         }
         if (!dup && pos < 8) {
 #pragma unroll
@@ -378,7 +390,6 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     ts[m] = v;
                 }
             }
-            if (tc < 8) ++tc;
         }
     };
 
@@ -585,9 +596,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             // one dart per table at a time (tickets in ascending order)
                             const uint32_t l = bucket_of(s, (uint32_t)k);
                             const int src = acc ? (int)l : lane;
-                            const uint32_t oc = (uint32_t)__shfl((int)tc, src, kWave);
                             const uint64_t omr = __shfl(tr[7], src, kWave), oms = __shfl(ts[7], src, kWave);
-                            bool pending = acc && (oc < 8 || rb < omr || (rb == omr && s <= oms));
+                            bool pending = acc && (rb < omr || (rb == omr && s <= oms));
                             if (wave_any(pending)) {
                                 int32_t* const ticket = &at<int32_t>(wb, kOffMark, 0);
                                 if (pending)
@@ -850,7 +860,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 }
                 bool filled = true;
                 if (RT) {
-                    filled = lane >= k || tc >= 8u;
+                    filled = lane >= k || tr[7] != kNoRank;
                 } else if (LSH) {
                     for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
                 } else {
@@ -869,7 +879,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             cut_r = ~0ull;
             cut_s = ~0ull;
         } else if (RT) {
-            tc = 0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) tr[m] = kNoRank;
         } else if (LSH) {
             for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
         } else {
