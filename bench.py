@@ -3,6 +3,15 @@
 One step = one dms_sketch_csr call over the whole batch (all sets, k minhashes
 plus 1-bit sketches), inputs resident in HBM.  Prints one JSON line.
 
+`roofline` prices the launch against the int-VALU peak: algorithmic work is
+one mixer evaluation per region, area, generated dart, rank-passing dart and
+accepted dart, counted exactly by the oracle on a sample of the batch, at the
+chip's measured lane-op cost of a mixer.  `frac` prices the paper's whole
+retry schedule (phi = 1, 2, ...), `frac_one_pass` its last pass alone.  The
+secondary lines (other workloads, estimators, fingerprints, the LSH index and
+the serving loop, which --serving-seconds 0 skips) follow the same pattern; each
+checks a sample of its outputs against the oracle.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch_k256]
 """
 from __future__ import annotations
