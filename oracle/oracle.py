@@ -160,15 +160,23 @@ COUNTER_DTYPE = np.dtype([("regions", "<i8"), ("areas", "<i8"), ("generated", "<
                           ("rank_pass", "<i8"), ("accepted", "<i8")])
 
 
-def build(force: bool = False) -> str:
-    """Compile dms_oracle.c with strict IEEE binary64 semantics."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+SAN_LIB = os.path.join(HERE, "libdms_oracle_san.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile dms_oracle.c with strict IEEE binary64 semantics.  With
+    `sanitize`, a second build of the same source under AddressSanitizer and
+    UndefinedBehaviorSanitizer (loaded only by the sanitizer test)."""
+    out = SAN_LIB if sanitize else LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        extra = (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer", "-g"] if sanitize else [])
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                                "-fno-finite-math-only", "-mfpmath=sse", "-msse2", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-shared", "-Wall"] + extra + ["-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -177,7 +185,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        L = ctypes.CDLL(build())
+        # DMS_ORACLE_LIB selects another build of the same source (the sanitizer build)
+        L = ctypes.CDLL(os.environ.get("DMS_ORACLE_LIB") or build())
         P = ctypes.POINTER
         vp = ctypes.c_void_p
         L.dmso_mix64.argtypes = [ctypes.c_uint64]

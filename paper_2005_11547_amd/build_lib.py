@@ -24,7 +24,8 @@ def build(verbose: bool = False) -> str:
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(bdir, s + ".o")
-        lang = ["-x", "hip"] if s.endswith(".hip") else ["-x", "hip"]
+        # kernels are HIP; the host-side runtime files are plain C++ against the HIP runtime API
+        lang = ["-x", "hip"] if s.endswith(".hip") else ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
         cmd = ["hipcc"] + FLAGS + lang + ["-c", src, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from jaccard import weighted_jaccard
 from oracle import oracle as O
 
 SEED = WL.HASH_SEED
@@ -50,7 +51,7 @@ def planted():
         beta = (0.2, 0.5, 0.8)[i % 3]
         (xi, xw), (yi, yw) = WL.paired_sets(rng, 48, 1.0, beta)
         rows += [(xi, xw), (yi, yw)]
-        js.append(WL.weighted_jaccard(xi, xw, yi, yw))
+        js.append(weighted_jaccard(xi, xw, yi, yw))
     rp, idx, w = WL.csr_from_rows(rows)
     ref = O.sketch_csr(rp, idx, w, 256, SEED)
     assert (ref["status"] == 0).all()

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from jaccard import weighted_jaccard
 from oracle import oracle as O
 from test_oracle_bruteforce import IDS, R_BOX, SEED, T, W_BOX, stream
 
@@ -95,7 +96,7 @@ def test_estimator_is_unbiased_on_planted_pairs():
     for i in range(120):
         (xi, xw), (yi, yw) = WL.paired_sets(rng, 40, 1.0, (0.2, 0.5, 0.8)[i % 3])
         rows += [(xi, xw), (yi, yw)]
-        js.append(WL.weighted_jaccard(xi, xw, yi, yw))
+        js.append(weighted_jaccard(xi, xw, yi, yw))
     js = np.array(js)
     k = 128
     rp, idx, w = WL.csr_from_rows(rows)

@@ -20,6 +20,7 @@ import pytest
 from scipy import stats
 
 import workloads as WL
+from jaccard import weighted_jaccard
 from oracle import oracle as O
 
 SEED = WL.HASH_SEED
@@ -182,7 +183,7 @@ def test_collision_rate_equals_weighted_jaccard_planted_pairs():
     m, J, bits_agree = [], [], []
     for p in range(len(rp) // 2):
         a, b = 2 * p, 2 * p + 1
-        Jp = WL.weighted_jaccard(idx[rp[a]:rp[a + 1]], w[rp[a]:rp[a + 1]],
+        Jp = weighted_jaccard(idx[rp[a]:rp[a + 1]], w[rp[a]:rp[a + 1]],
                                  idx[rp[b]:rp[b + 1]], w[rp[b]:rp[b + 1]])
         J.append(Jp)
         m.append(int((out["u32"][a] == out["u32"][b]).sum()))
@@ -229,7 +230,7 @@ def test_lsh_key_collision_is_J_to_the_K():
     for p in range(25):
         Jt = [0.5, 0.8, 0.95][p % 3]
         (xi, xw), (yi, yw) = WL.paired_sets(rng, int(rng.integers(20, 200)), 1.0, 2 * Jt / (1 + Jt))
-        J = WL.weighted_jaccard(xi, xw, yi, yw)
+        J = weighted_jaccard(xi, xw, yi, yw)
         st1, k1, *_ = O.lsh_set(xi, xw, L, K, SEED)
         st2, k2, *_ = O.lsh_set(yi, yw, L, K, SEED)
         assert st1 == 0 and st2 == 0
@@ -247,7 +248,7 @@ def test_estimation_experiment_coverage():
     for k in range(1, 101, 3):
         for Jt in (0.25, 0.5, 0.75):
             (xi, xw), (yi, yw) = WL.paired_sets(rng, 256, 1.0, 2 * Jt / (1 + Jt))
-            J = WL.weighted_jaccard(xi, xw, yi, yw)
+            J = weighted_jaccard(xi, xw, yi, yw)
             seed = int(rng.integers(1, 2 ** 63))
             a = _minhash(xi, xw, k, seed=seed)[0]
             b = _minhash(yi, yw, k, seed=seed)[0]

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from jaccard import weighted_jaccard
 from oracle import oracle as O
 from test_oracle_bruteforce import IDS, NU, R_BOX, RHO, SEED, T, hitting, key, random_sets, stream
 
@@ -67,7 +68,7 @@ def test_collision_law_and_schedule_independence():
     for i in range(90):
         (xi, xw), (yi, yw) = WL.paired_sets(rng, 40, 1.0, (0.2, 0.5, 0.8)[i % 3])
         rows += [(xi, xw), (yi, yw)]
-        js.append(WL.weighted_jaccard(xi, xw, yi, yw))
+        js.append(weighted_jaccard(xi, xw, yi, yw))
     js = np.array(js)
     rp, idx, w = WL.csr_from_rows(rows)
     k = 256

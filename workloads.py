@@ -224,13 +224,3 @@ def csr_from_rows(rows):
     idx = np.concatenate([np.asarray(r[0], dtype=np.int32) for r in rows]) if rows else np.zeros(0, np.int32)
     w = np.concatenate([np.asarray(r[1], dtype=np.float64) for r in rows]) if rows else np.zeros(0)
     return _row_ptr(nnz), idx, w
-
-
-def weighted_jaccard(ia, wa, ib, wb) -> float:
-    """Closed form J(x,y) = sum min / sum max (eq. 1) for two sparse rows."""
-    a = dict(zip(np.asarray(ia).tolist(), np.asarray(wa).tolist()))
-    b = dict(zip(np.asarray(ib).tolist(), np.asarray(wb).tolist()))
-    keys = set(a) | set(b)
-    num = sum(min(a.get(i, 0.0), b.get(i, 0.0)) for i in keys)
-    den = sum(max(a.get(i, 0.0), b.get(i, 0.0)) for i in keys)
-    return num / den
