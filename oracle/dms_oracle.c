@@ -61,8 +61,13 @@ typedef struct {
     uint64_t s;     /* dart id hash                      */
 } dmso_dart;
 
+/* Enumeration counts of DartHash passes: regions and areas visited, darts
+ * generated, darts with rank <= tau, darts accepted (rank <= tau and weight <=
+ * x_i); rank_new and accepted_new count the last two restricted to ranks above
+ * the previous pass's tau (every dart of the first pass is new).  A retry that
+ * only inserts darts it has not met before needs exactly the new ones. */
 typedef struct {
-    int64_t regions, areas, generated, rank_pass, accepted;
+    int64_t regions, areas, generated, rank_pass, accepted, rank_new, accepted_new;
 } dmso_counters;
 
 /* SplitMix64 output function (bijective 64 -> 64 bit mixer). */
@@ -138,11 +143,15 @@ static int push_dart(dart_list* L, const dmso_dart* x)
  * height delta_rho = 2^rho/2^nu, so every area has size 1/t and holds
  * Poisson(1) darts.
  *
+ * tau_prev only steers the rank_new / accepted_new counts (the previous
+ * pass's tau; below every rank on a first pass).
+ *
  * Returns DMSO_OK, DMSO_RANGE (a subdivision index or table index out of the
  * supported range) or DMSO_NOMEM.
  */
 static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
-                    const double* x, double tau, dart_list* out, dmso_counters* cnt)
+                    const double* x, double tau, double tau_prev, dart_list* out,
+                    dmso_counters* cnt)
 {
     for (int64_t e = 0; e < nnz; e++) {
         double xi = x[e];
@@ -178,7 +187,9 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
                             double rank = Rr + (rd + U) * drho;
                             cnt->generated++;
                             if (rank <= tau) cnt->rank_pass++;
+                            if (rank <= tau && rank > tau_prev) cnt->rank_new++;
                             if (weight <= xi && rank <= tau) {
+                                if (rank > tau_prev) cnt->accepted_new++;
                                 dmso_dart D;
                                 D.i = id; D.nu = (uint16_t)nu; D.rho = (uint16_t)rho;
                                 D.w = w; D.r = r; D.j = j; D.pad = 0;
@@ -240,7 +251,7 @@ int dmso_darthash(const dmso_params* P, int64_t nnz, const int32_t* idx, const d
     dart_list L = {0, 0, 0};
     dmso_counters c;
     memset(&c, 0, sizeof c);
-    int st = darthash(P, nnz, idx, x, tau, &L, &c);
+    int st = darthash(P, nnz, idx, x, tau, -1.0, &L, &c);
     int64_t n = L.n < cap ? L.n : cap;
     if (out && n > 0) memcpy(out, L.d, (size_t)n * sizeof(dmso_dart));
     *n_out = L.n;
@@ -262,6 +273,8 @@ static void count_pass(dmso_counters* cnt, const dmso_counters* c)
     cnt[0].generated += c->generated;
     cnt[0].rank_pass += c->rank_pass;
     cnt[0].accepted += c->accepted;
+    cnt[0].rank_new += c->rank_new;
+    cnt[0].accepted_new += c->accepted_new;
     cnt[1] = *c;
 }
 
@@ -281,7 +294,7 @@ int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
     int st = check_row(nnz, x, &S);
     if (st != DMSO_OK) return st;
     int filled = 0;
-    double phi = P->phi0;
+    double phi = P->phi0, tau_prev = -1.0;
     uint8_t* have = (uint8_t*)malloc((size_t)k);
     if (!have) return DMSO_NOMEM;
     for (;;) {
@@ -290,7 +303,8 @@ int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
         dart_list L = {0, 0, 0};
         dmso_counters c;
         memset(&c, 0, sizeof c);
-        st = darthash(P, nnz, idx, x, tau, &L, &c);
+        st = darthash(P, nnz, idx, x, tau, tau_prev, &L, &c);
+        tau_prev = tau;
         count_pass(cnt, &c);
         if (st != DMSO_OK) { free(L.d); break; }
         memset(have, 0, (size_t)k);
@@ -376,14 +390,15 @@ int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const 
     double* br = (double*)malloc(slots * sizeof(double));
     int32_t* cnt = (int32_t*)malloc((size_t)L * sizeof(int32_t));
     if (!bs || !br || !cnt) { free(bs); free(br); free(cnt); return DMSO_NOMEM; }
-    double phi = P->phi0;
+    double phi = P->phi0, tau_prev = -1.0;
     for (;;) {
         if (phi > P->phi_max) { st = DMSO_RANGE; break; }
         double tau = phi / S;
         dart_list D = {0, 0, 0};
         dmso_counters c;
         memset(&c, 0, sizeof c);
-        st = darthash(P, nnz, idx, x, tau, &D, &c);
+        st = darthash(P, nnz, idx, x, tau, tau_prev, &D, &c);
+        tau_prev = tau;
         count_pass(pass_cnt, &c);
         if (st != DMSO_OK) { free(D.d); break; }
         for (int32_t l = 0; l < L; l++) cnt[l] = 0;
@@ -472,13 +487,14 @@ int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
     double S;
     int st = check_row(nnz, x, &S);
     if (st != DMSO_OK) return st;
-    double phi = P->phi0;
+    double phi = P->phi0, tau_prev = -1.0;
     for (;;) {
         if (phi > P->phi_max) return DMSO_RANGE;
         dart_list L = {0, 0, 0};
         dmso_counters c;
         memset(&c, 0, sizeof c);
-        st = darthash(P, nnz, idx, x, phi / S, &L, &c);
+        st = darthash(P, nnz, idx, x, phi / S, tau_prev, &L, &c);
+        tau_prev = phi / S;
         count_pass(cnt, &c);
         if (st != DMSO_OK) { free(L.d); return st; }
         if (L.n > 1) qsort(L.d, (size_t)L.n, sizeof(dmso_dart), cmp_dart);

@@ -150,14 +150,16 @@ class Params(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("regions", ctypes.c_int64), ("areas", ctypes.c_int64),
                 ("generated", ctypes.c_int64), ("rank_pass", ctypes.c_int64),
-                ("accepted", ctypes.c_int64)]
+                ("accepted", ctypes.c_int64), ("rank_new", ctypes.c_int64),
+                ("accepted_new", ctypes.c_int64)]
 
 
 DART_DTYPE = np.dtype([("i", "<u4"), ("nu", "<u2"), ("rho", "<u2"), ("w", "<u4"), ("r", "<u4"),
                        ("j", "<u4"), ("pad", "<u4"), ("rank", "<f8"), ("weight", "<f8"),
                        ("s", "<u8")])
 COUNTER_DTYPE = np.dtype([("regions", "<i8"), ("areas", "<i8"), ("generated", "<i8"),
-                          ("rank_pass", "<i8"), ("accepted", "<i8")])
+                          ("rank_pass", "<i8"), ("accepted", "<i8"), ("rank_new", "<i8"),
+                          ("accepted_new", "<i8")])
 
 
 SAN_LIB = os.path.join(HERE, "libdms_oracle_san.so")

@@ -75,3 +75,44 @@ def test_schedule_sums_equal_single_passes(kind):
         passes = [_pass(ids, ww, float(p), t)[0] for p in range(1, final + 1)]
         assert np.array_equal(tot[q], np.sum(passes, axis=0)), (kind, q)
         assert np.array_equal(last[q], passes[-1]), (kind, q)
+
+
+@pytest.mark.parametrize("kind", ["minhash", "bottomk", "lsh"])
+@pytest.mark.parametrize("phi0", [1.0, 1.3])
+def test_new_darts_of_a_doubling_schedule(kind, phi0):
+    # Lemma 1: a pass at tau returns every dart of rank <= tau, so the bands
+    # (tau_prev, tau] of the passes partition the darts of the last pass: the
+    # new counts sum to the last pass's counts, and a pass's accepted new darts
+    # are exactly its returned darts above the previous tau
+    rows = _rows(3, 10)
+    rp, idx, w = WL.csr_from_rows(rows)
+    sched = O.SCHED_DOUBLE
+    if kind == "minhash":
+        k, t = 64, O.t_of_k(64)
+        r = O.sketch_csr(rp, idx, w, k, SEED, phi0=phi0, schedule=sched, full=True)
+        tot, last, phis = r["counters"], r["counters_last"], r["phi"]
+    elif kind == "bottomk":
+        k = t = 32
+        r = O.bottomk_csr(rp, idx, w, k, SEED, phi0=phi0, schedule=sched, counters=True)
+        tot, last = r["counters"][:, 0], r["counters"][:, 1]
+        phis = [O.bottomk_set(ids, ww, k, SEED, phi0=phi0, schedule=sched)[3] for ids, ww in rows]
+    else:
+        L, K = 8, 4
+        t = L * K
+        r = O.lsh_csr(rp, idx, w, L, K, SEED, phi0=phi0, schedule=sched, counters=True)
+        tot, last = r["counters"][:, 0], r["counters"][:, 1]
+        phis = [O.lsh_set(ids, ww, L, K, SEED, phi0=phi0, schedule=sched)[4] for ids, ww in rows]
+    assert (r["status"] == 0).all()
+    for q, (ids, ww) in enumerate(rows):
+        assert tot[q]["rank_new"] == last[q]["rank_pass"]
+        assert tot[q]["accepted_new"] == last[q]["accepted"]
+        S = O.seq_sum(ww)
+        phi, tau_prev, acc_new = phi0, -1.0, 0
+        while phi <= phis[q]:
+            st, darts, c = O.darthash(ids, ww, phi / S, t, SEED)
+            acc_new += int(np.count_nonzero(darts["rank"] > tau_prev))
+            tau_prev = phi / S
+            phi *= 2.0
+        assert acc_new == tot[q]["accepted_new"]
+        if phis[q] == phi0:  # one pass: every dart is new
+            assert tot[q]["rank_new"] == tot[q]["rank_pass"] and tot[q]["accepted_new"] == tot[q]["accepted"]
