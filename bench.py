@@ -3,14 +3,18 @@
 One step = one dms_sketch_csr call over the whole batch (all sets, k minhashes
 plus 1-bit sketches), inputs resident in HBM.  Prints one JSON line.
 
-`roofline` prices the launch against the int-VALU peak: algorithmic work is
-one mixer evaluation per region, area, generated dart, rank-passing dart and
-accepted dart, counted exactly by the oracle on a sample of the batch, at the
-chip's measured lane-op cost of a mixer.  `frac` prices the paper's whole
-retry schedule (phi = 1, 2, ...), `frac_one_pass` its last pass alone.  The
-secondary lines (other workloads, estimators, fingerprints, the LSH index and
-the serving loop, which --serving-seconds 0 skips) follow the same pattern; each
-checks a sample of its outputs against the oracle.
+`roofline` prices the main kernel against the int-VALU peak: algorithmic work
+is one mixer evaluation per region, area, generated dart, rank-passing dart and
+accepted dart, as the GPU itself counts them over the whole batch
+(DMS_FLAG_COUNTERS, one extra untimed call), at the chip's measured lane-op
+cost of a mixer, divided by the main kernel's average duration over the timed
+steps (HIP events around that kernel on its stream, DMS_OPT_TIMING).  The
+oracle, run on a sample of the sets at the same schedule, must report the same
+counts for them; `frac_paper_schedule` prices the paper's retry schedule
+(phi = 1, 2, ...) from the oracle's counts instead.  The secondary lines (other
+workloads, estimators, fingerprints, the LSH index and the serving loop, which
+--serving-seconds 0 skips) follow the same pattern; each checks a sample of its
+outputs against the oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch_k256]
 """
@@ -49,16 +53,125 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_work(counters, c_mix):
-    """Lane-op equivalents per set, from the oracle's exact enumeration counts:
-    one mixer per region, area, generated dart (rank uniform), rank-passing
-    dart (weight uniform) and accepted dart (id hash), each costing c_mix, plus
-    8 lane-ops per dart uniform (53-bit conversion and the three FP64
-    operations of the rank or weight formula, and its compare)."""
-    H = (counters["regions"] + counters["areas"] + counters["generated"] +
-         counters["rank_pass"] + counters["accepted"]).astype(np.float64)
-    extra = 8.0 * (counters["generated"] + counters["rank_pass"]).astype(np.float64)
+def algorithmic_work(counters, c_mix, band=False):
+    """Lane-op equivalents per set, from exact enumeration counts (the oracle's
+    counter records, or the GPU's int64 [n, 8] rows): one mixer per region,
+    area, generated dart (rank uniform), rank-passing dart (weight uniform) and
+    accepted dart (id hash), each costing c_mix, plus 8 lane-ops per dart
+    uniform (53-bit conversion and the three FP64 operations of the rank or
+    weight formula, and its compare).  With `band` the oracle's rank and
+    acceptance counts of each pass's new band are used (what a retry that keeps
+    its darts needs)."""
+    if isinstance(counters, np.ndarray) and counters.dtype.names is None:
+        c = counters.astype(np.float64)
+        reg, area, gen, rank, acc = c[:, 0], c[:, 1], c[:, 2], c[:, 3], c[:, 4]
+    else:
+        reg, area, gen = (counters[f].astype(np.float64) for f in ("regions", "areas", "generated"))
+        rank = counters["rank_new" if band else "rank_pass"].astype(np.float64)
+        acc = counters["accepted_new" if band else "accepted"].astype(np.float64)
+    H = reg + area + gen + rank + acc
+    extra = 8.0 * (gen + rank)
     return H, c_mix * H + extra
+
+
+def gpu_counts(run_with_counters, n, torch):
+    """int64 [n, 8] enumeration counts of one untimed call with DMS_FLAG_COUNTERS."""
+    cnt = torch.empty((n, 8), dtype=torch.int64, device="cuda")
+    run_with_counters(cnt)
+    torch.cuda.synchronize()
+    out = cnt.cpu().numpy()
+    del cnt
+    return out
+
+
+def cpu_info():
+    """CPU model and logical cores of this host (lscpu)."""
+    import subprocess
+    info = {"model": None, "logical_cpus": os.cpu_count()}
+    try:
+        text = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in text.splitlines():
+            if line.startswith("Model name:"):
+                info["model"] = line.split(":", 1)[1].strip()
+            elif line.startswith("Socket(s):"):
+                info["sockets"] = int(line.split(":", 1)[1])
+            elif line.startswith("Core(s) per socket:"):
+                info["cores_per_socket"] = int(line.split(":", 1)[1])
+    except Exception:
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return info
+
+
+def _oracle_shard(args):
+    """One worker of the all-core baseline: the oracle over its rows."""
+    from oracle import oracle as O
+    rp, idx, w, k = args
+    t0 = time.perf_counter()
+    O.sketch_csr(rp, idx, w, k, WL.HASH_SEED)
+    return len(rp) - 1, time.perf_counter() - t0
+
+
+def _rows(rp, idx, w, rows):
+    sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
+    sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows]) if len(rows) else idx[:0]
+    sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows]) if len(rows) else w[:0]
+    return sub_rp, sub_idx, sub_w
+
+
+def cpu_all_cores(rp, idx, w, k, stride, workers):
+    """The oracle on every `stride`-th set, as `workers` processes over
+    contiguous shards of about equal nonzeros (forked before the GPU is used).
+    Returns (sets/s of the whole sample, sets, workers, wall seconds)."""
+    import multiprocessing as mp
+    rows = np.arange(0, len(rp) - 1, stride)
+    sub_rp, sub_idx, sub_w = _rows(rp, idx, w, rows)
+    cuts = np.searchsorted(sub_rp, np.linspace(0, sub_rp[-1], workers + 1)[1:-1])
+    bounds = [0] + [int(c) for c in cuts] + [len(rows)]
+    shards = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        if b > a:
+            shards.append((sub_rp[a:b + 1] - sub_rp[a], sub_idx[sub_rp[a]:sub_rp[b]],
+                           sub_w[sub_rp[a]:sub_rp[b]], k))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(shards)) as pool:
+        done = pool.map(_oracle_shard, shards)
+    wall = time.perf_counter() - t0
+    n = sum(d[0] for d in done)
+    return n / wall, n, len(shards), wall
+
+
+def cpu_configs(seconds_each=4.0):
+    """Single-core oracle sets/s on the other configurations (row samples, each
+    under a time budget): plain_k64 (all 1,400 rows), uneven_k1024 (every
+    100th set), lsh_L64K8 ((64,8) keys; 10,000 sets drawn from the same
+    generator)."""
+    from oracle import oracle as O
+    out = {}
+    cases = (("plain_k64", lambda: WL.plain_k64()[:3], 1, "sketch", 64),
+             ("uneven_k1024", lambda: WL.uneven_k1024(), 100, "sketch", 1024),
+             ("lsh_L64K8", lambda: WL.lsh_L64K8(n_sets=10_000), 1, "lsh", None))
+    for name, gen, stride, kind, k in cases:
+        rp, idx, w = gen()
+        rows = np.arange(0, len(rp) - 1, stride)
+        got, t_cpu, chunk = 0, 0.0, 32
+        while got < len(rows) and t_cpu < seconds_each:
+            sel = rows[got:got + chunk]
+            c_rp, c_idx, c_w = _rows(rp, idx, w, sel)
+            t0 = time.perf_counter()
+            if kind == "sketch":
+                O.sketch_csr(c_rp, c_idx, c_w, k, WL.HASH_SEED)
+            else:
+                O.lsh_csr(c_rp, c_idx, c_w, 64, 8, WL.HASH_SEED)
+            t_cpu += time.perf_counter() - t0
+            got += len(sel)
+        out[name] = {"sets_per_s": got / t_cpu, "sets": int(got), "seconds": t_cpu,
+                     "sample": f"every {stride}th set" if stride > 1 else "all sets"}
+        log(f"cpu baseline {name}: {out[name]}")
+    return out
 
 
 def calibrate_mixer(ctx, torch, n_cu):
@@ -156,8 +269,9 @@ def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
     (L,K) = (64,8) LSH keys, bottom-k sketches with k = 256 of the main batch,
     and the main batch under the tabulation-hash variant), each checked bit for
     bit on a row sample; for the uneven batch, the LSH keys and bottom-k also
-    the fraction of the int-VALU peak, from the oracle's enumeration counts on a
-    sample of the sets."""
+    the fraction of the int-VALU peak, priced on the GPU's own enumeration
+    counts over the whole batch and the main kernel's event-timed duration (the
+    oracle's counts at the same schedule must equal the GPU's on the sample)."""
     from oracle import oracle as O
     from paper_2005_11547_amd import Context, dms, to_device
     res = {}
@@ -176,34 +290,39 @@ def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
             run_ctx.set_option(dms.OPT_HASH, dms.HASH_TAB)
             out = torch.empty((n, 256), dtype=torch.int32, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
-            run = lambda: run_ctx.dms_sketch_csr(n, d[0], d[1], d[2], 256, out, None, st)
+            run = lambda f=0, c=None: run_ctx.dms_sketch_csr(n, d[0], d[1], d[2], 256, out, None, st, flags=f,
+                                                            out_counters=c)
         elif kind == "sketch":
             out = torch.empty((n, 1024), dtype=torch.int32, device="cuda")
             bits = torch.empty((n, 16), dtype=torch.int64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
-            run = lambda: ctx.dms_sketch_csr(n, d[0], d[1], d[2], 1024, out, bits, st)
+            run = lambda f=0, c=None: ctx.dms_sketch_csr(n, d[0], d[1], d[2], 1024, out, bits, st, flags=f,
+                                                        out_counters=c)
         elif kind == "lsh":
             out = torch.empty((n, 64), dtype=torch.int64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
-            run = lambda: ctx.dms_lsh_keys(n, d[0], d[1], d[2], 64, 8, out, st)
+            run = lambda f=0, c=None: ctx.dms_lsh_keys(n, d[0], d[1], d[2], 64, 8, out, st, flags=f, out_counters=c)
         else:
             out = torch.empty((n, 256), dtype=torch.int64, device="cuda")
             rk = torch.empty((n, 256), dtype=torch.float64, device="cuda")
             st = torch.empty(n, dtype=torch.int8, device="cuda")
-            run = lambda: ctx.dms_bottomk(n, d[0], d[1], d[2], 256, out, rk, st)
+            run = lambda f=0, c=None: ctx.dms_bottomk(n, d[0], d[1], d[2], 256, out, rk, st, flags=f, out_counters=c)
         run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        run_ctx.set_option(dms.OPT_TIMING, 1)
+        run_ctx.kernel_time()
         e0.record()
         for _ in range(steps):
             run()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        k_total, k_n = run_ctx.kernel_time()
+        run_ctx.set_option(dms.OPT_TIMING, 0)
+        kernel_ms = k_total / max(k_n, 1)
         rows = np.linspace(0, n - 1, 200).astype(np.int64)
-        sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
-        sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
-        sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
+        sub_rp, sub_idx, sub_w = _rows(rp, idx, w, rows)
         got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
         if kind == "tabulation":
             ref = O.sketch_csr(sub_rp, sub_idx, sub_w, 256, WL.HASH_SEED, hash=O.HASH_TAB)["u32"]
@@ -219,58 +338,51 @@ def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
             exact = bool(np.array_equal(got.view(np.uint64), ref["s"]) and
                          np.array_equal(rk[torch.from_numpy(rows).cuda()].cpu().numpy(), ref["rank"]))
         res[name] = {"sets_per_s": n / (ms * 1e-3), "nnz_per_s": float(rp[-1]) / (ms * 1e-3),
-                     "ms_per_step": ms, "n_sets": n, "bit_exact_sample": {"sets_checked": 200, "exact": exact}}
-        if kind == "sketch" and c_mix is not None:
-            # algorithmic work of the batch from the oracle's counts on every 20th set
-            rows = np.arange(0, n, 20)
-            sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
-            sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
-            sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
-            r = O.sketch_csr(sub_rp, sub_idx, sub_w, 1024, WL.HASH_SEED, full=True)
-            same = bool(np.array_equal(out[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32), r["u32"]))
-            H, ops = algorithmic_work(r["counters"], c_mix)
-            achieved = float(ops.mean()) * n / (ms * 1e-3) / 1e12
-            _, ops1 = algorithmic_work(r["counters_last"], c_mix)
-            res[name]["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
-                                     "unit": "T int32 lane-op/s", "frac": achieved / PEAK_INT_TOPS,
-                                     "frac_one_pass": float(ops1.mean()) * n / (ms * 1e-3) / 1e12 / PEAK_INT_TOPS,
-                                     "mixers_per_set": float(H.mean()),
-                                     "sample": f"every 20th set ({len(rows)} sets), bit-exact: {same}"}
-        elif kind in ("lsh", "bottomk") and c_mix is not None:
-            # algorithmic work from the oracle's counts on every 50th set.  The
-            # paper's schedule (phi = 1, 2, 3, ...) repeats whole passes, most
-            # of them for LSH, whose first pass never fills every table, so the
-            # fraction is priced on the last pass alone (one DartHash pass at
-            # the final phi, the least work of that schedule); the full
-            # schedule's figure is kept beside it
-            rows = np.arange(0, n, 50)
-            sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
-            sub_idx = np.concatenate([idx[rp[r]:rp[r + 1]] for r in rows])
-            sub_w = np.concatenate([w[rp[r]:rp[r + 1]] for r in rows])
-            if kind == "lsh":
-                r = O.lsh_csr(sub_rp, sub_idx, sub_w, 64, 8, WL.HASH_SEED, counters=True)
-                same = bool(np.array_equal(out[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint64),
-                                           r["keys"]))
+                     "ms_per_step": ms, "kernel_ms": kernel_ms, "n_sets": n,
+                     "bit_exact_sample": {"sets_checked": 200, "exact": exact}}
+        if kind != "tabulation" and c_mix is not None:
+            # the GPU's own counts over the whole batch; the oracle at the same
+            # schedule on every 50th set must count the same
+            g_cnt = gpu_counts(lambda c: run(dms.FLAG_COUNTERS, c), n, torch)
+            srows = np.arange(0, n, 50)
+            s_rp, s_idx, s_w = _rows(rp, idx, w, srows)
+            if kind == "sketch":
+                r = O.sketch_csr(s_rp, s_idx, s_w, 1024, WL.HASH_SEED, phi0=ctx.get_option(dms.OPT_PHI0),
+                                 schedule=O.SCHED_DOUBLE, full=True)
+                rc, paper = r["counters"], O.sketch_csr(s_rp, s_idx, s_w, 1024, WL.HASH_SEED, full=True)["counters"]
+                fold = 0
+            elif kind == "lsh":
+                r = O.lsh_csr(s_rp, s_idx, s_w, 64, 8, WL.HASH_SEED, phi0=ctx.get_option(dms.OPT_LSH_PHI0),
+                              schedule=O.SCHED_DOUBLE, counters=True)
+                rc, paper = r["counters"][:, 0], O.lsh_csr(s_rp, s_idx, s_w, 64, 8, WL.HASH_SEED,
+                                                            counters=True)["counters"][:, 0]
                 fold = 64 * (8 + 1)  # the key of each table folds its K ids, one mixer each, plus its seed
             else:
-                r = O.bottomk_csr(sub_rp, sub_idx, sub_w, 256, WL.HASH_SEED, counters=True)
-                same = bool(np.array_equal(out[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint64),
-                                           r["s"]))
+                r = O.bottomk_csr(s_rp, s_idx, s_w, 256, WL.HASH_SEED, phi0=1.0 + 4.0 / 16.0,
+                                  schedule=O.SCHED_DOUBLE, counters=True)
+                rc, paper = r["counters"][:, 0], O.bottomk_csr(s_rp, s_idx, s_w, 256, WL.HASH_SEED,
+                                                                counters=True)["counters"][:, 0]
                 fold = 0
-            ok = r["status"] == 0
-            H1, ops1 = algorithmic_work(r["counters"][:, 1], c_mix)
-            Hs, opss = algorithmic_work(r["counters"][:, 0], c_mix)
-            per_set = float(ops1[ok].mean()) + c_mix * fold
-            achieved = per_set * n / (ms * 1e-3) / 1e12
+            okr = r["status"] == 0
+            names = ("regions", "areas", "generated", "rank_new", "accepted_new")
+            same = bool(all(np.array_equal(g_cnt[srows][okr, q], rc[nm][okr]) for q, nm in enumerate(names)))
+            ok_all = st.cpu().numpy() == 0
+            H, ops = algorithmic_work(g_cnt[ok_all], c_mix)
+            total = float(ops.sum()) + c_mix * fold * float(ok_all.sum())
+            achieved = total / (kernel_ms * 1e-3) / 1e12
+            Hp, opsp = algorithmic_work(paper[okr], c_mix)
             res[name]["roofline"] = {
                 "bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "T int32 lane-op/s",
-                "frac": achieved / PEAK_INT_TOPS,
-                "frac_paper_schedule": (float(opss[ok].mean()) + c_mix * fold) * n / (ms * 1e-3) / 1e12
-                / PEAK_INT_TOPS,
-                "mixers_per_set": float(H1[ok].mean()) + fold,
-                "mixers_per_set_paper_schedule": float(Hs[ok].mean()) + fold,
-                "sample": f"every 50th set ({len(rows)} sets), bit-exact: {same}"}
+                "frac": achieved / PEAK_INT_TOPS, "work": "the GPU's own enumeration counts over the whole batch",
+                "mixers_per_set": float(H.mean()) + fold,
+                "counts_equal_oracle_sample": same,
+                "frac_paper_schedule": (float(opsp.mean()) + c_mix * fold) * float(ok_all.sum())
+                / (kernel_ms * 1e-3) / 1e12 / PEAK_INT_TOPS,
+                "mixers_per_set_paper_schedule": float(Hp.mean()) + fold,
+                "sample": f"oracle counts on every 50th set ({len(srows)} sets)"}
         log(f"{name}: {res[name]}")
+        if run_ctx is not ctx:
+            run_ctx.close()
         del d, out
     return res
 
@@ -461,6 +573,10 @@ def main():
                     help="time budget of the oracle CPU baseline (0 disables it)")
     ap.add_argument("--cpu-stride", type=int, default=25,
                     help="oracle sample: every n-th set")
+    ap.add_argument("--cpu-all-stride", type=int, default=10,
+                    help="all-core oracle baseline: every n-th set")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="all-core oracle baseline: at most this many processes")
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the served trace at 50k requests/s (0 disables serving)")
     ap.add_argument("--serving-db", type=int, default=1_000_000, help="database rows")
@@ -496,6 +612,19 @@ def main():
     nnz = int(rp[-1])
     log(f"{args.workload}: {n_sets} sets, {nnz} nnz generated in {time.time() - t0:.1f}s")
 
+    # CPU baselines first: the all-core run forks worker processes, which must
+    # happen before this process touches the GPU
+    host = cpu_info()
+    all_core = None
+    if args.cpu_seconds > 0:
+        workers = max(1, min(args.cpu_workers, host.get("affinity_cpus") or os.cpu_count() or 1))
+        rate, n_all, used, wall = cpu_all_cores(rp, idx, w, k, args.cpu_all_stride, workers)
+        all_core = {"value": rate, "unit": "sets/s", "cores": used, "kind": "oracle",
+                    "sample": f"every {args.cpu_all_stride}th set ({n_all} sets) in {used} processes over "
+                              f"shards of equal nonzeros, {wall:.1f}s wall"}
+        log(f"cpu baseline all cores: {all_core}")
+    other_cfgs = cpu_configs() if args.cpu_seconds > 0 else None
+
     d_rp, d_idx, d_w = to_device(rp, idx, w)
     out_u32 = torch.empty((n_sets, k), dtype=torch.int32, device="cuda")
     words = (k + 63) // 64
@@ -525,6 +654,8 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.set_option(dms.OPT_TIMING, 1)  # events around the main kernel of each step
+    ctx.kernel_time()
     wall0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -533,11 +664,19 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = e0.elapsed_time(e1) / args.steps
-    log(f"{args.steps} steps: {ms:.3f} ms/step (events), {wall / args.steps * 1e3:.3f} ms/step (wall)")
+    k_total, k_launches = ctx.kernel_time()
+    ctx.set_option(dms.OPT_TIMING, 0)
+    kernel_ms = k_total / max(k_launches, 1)
+    log(f"{args.steps} steps: {ms:.3f} ms/step (events), {wall / args.steps * 1e3:.3f} ms/step (wall), "
+        f"main kernel {kernel_ms:.3f} ms ({k_launches} launches)")
 
     sets_per_s = n_sets / (ms * 1e-3)
     nnz_per_s = nnz / (ms * 1e-3)
     status = out_status.cpu().numpy()
+
+    # the GPU's own enumeration counts over the whole batch (one untimed call)
+    g_cnt = gpu_counts(lambda c: ctx.dms_sketch_csr(n_sets, d_rp, d_idx, d_w, k, out_u32, out_bits, out_status,
+                                                    flags=dms.FLAG_COUNTERS, out_counters=c), n_sets, torch)
 
     # roofline: algorithmic integer work per launch / launch duration
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
@@ -548,41 +687,46 @@ def main():
     from oracle import oracle as O
     stride = max(1, args.cpu_stride)
     sample = np.arange(0, n_sets, stride)
-    sub_rp = np.concatenate([[0], np.cumsum(rp[sample + 1] - rp[sample])]).astype(np.int64)
-    sub_idx = np.concatenate([idx[rp[s]:rp[s + 1]] for s in sample])
-    sub_w = np.concatenate([w[rp[s]:rp[s + 1]] for s in sample])
-    # the oracle runs on the sample under a time budget (the CPU baseline)
+    sub_rp, sub_idx, sub_w = _rows(rp, idx, w, sample)
+    # the oracle at the GPU's schedule (first phi, doubling) on the sample under
+    # a time budget: the single-core CPU baseline, the outputs and the counts
     got = 0
     t_cpu = 0.0
     chunk = 64
-    ref_u32, ref_bits, ref_st, cnts, cnts1 = [], [], [], [], []
+    ref_u32, ref_bits, ref_st, cnts = [], [], [], []
     while got < len(sample) and (t_cpu < max(args.cpu_seconds, 1.0)):
         hi = min(len(sample), got + chunk)
         c_rp = sub_rp[got:hi + 1] - sub_rp[got]
         c_idx = sub_idx[sub_rp[got]:sub_rp[hi]]
         c_w = sub_w[sub_rp[got]:sub_rp[hi]]
         tc = time.perf_counter()
-        r = O.sketch_csr(c_rp, c_idx, c_w, k, WL.HASH_SEED, full=True)
+        r = O.sketch_csr(c_rp, c_idx, c_w, k, WL.HASH_SEED, phi0=schedule["phi0"], schedule=O.SCHED_DOUBLE,
+                         full=True)
         t_cpu += time.perf_counter() - tc
         ref_u32.append(r["u32"]); ref_bits.append(r["bits"]); ref_st.append(r["status"])
         cnts.append(r["counters"])
-        cnts1.append(r["counters_last"])
         got = hi
     rows = sample[:got]
     ref_u32 = np.concatenate(ref_u32); ref_bits = np.concatenate(ref_bits)
-    ref_st = np.concatenate(ref_st); cnts = np.concatenate(cnts); cnts1 = np.concatenate(cnts1)
+    ref_st = np.concatenate(ref_st); cnts = np.concatenate(cnts)
     gpu_u32 = out_u32[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32)
     gpu_bits = out_bits[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint64)
     exact = bool(np.array_equal(gpu_u32, ref_u32) and np.array_equal(gpu_bits, ref_bits)
                  and np.array_equal(status[rows], ref_st))
-    log(f"oracle sample: {got} sets in {t_cpu:.1f}s; GPU bit-exact on them: {exact}")
+    okr = ref_st == 0
+    names = ("regions", "areas", "generated", "rank_new", "accepted_new")
+    counts_equal = bool(all(np.array_equal(g_cnt[rows][okr, q], cnts[name][okr]) for q, name in enumerate(names)))
+    log(f"oracle sample: {got} sets in {t_cpu:.1f}s; GPU bit-exact on them: {exact}; counts equal: {counts_equal}")
+    # the paper's schedule (phi = 1, 2, 3, ...) on a smaller sample, for context
+    p_rows = np.arange(0, n_sets, stride * 10)
+    pr = O.sketch_csr(*_rows(rp, idx, w, p_rows), k, WL.HASH_SEED, full=True)
+    Hp, opsp = algorithmic_work(pr["counters"], c_mix)
 
-    H, ops = algorithmic_work(cnts, c_mix)
-    _, ops1 = algorithmic_work(cnts1, c_mix)
-    ok = ref_st == 0
-    ops_per_set = float(ops[ok].mean()) if ok.any() else 0.0
-    ops_launch = ops_per_set * n_sets
-    achieved = ops_launch / (ms * 1e-3) / 1e12
+    ok_all = status == 0
+    H, ops = algorithmic_work(g_cnt[ok_all], c_mix)
+    ops_launch = float(ops.sum())
+    achieved = ops_launch / (kernel_ms * 1e-3) / 1e12
+    okp = pr["status"] == 0
     hbm_bytes = 8.0 * (n_sets + 1) + 12.0 * nnz + n_sets * (4.0 * k + 8.0 * words + 1.0)
 
     traffic = None
@@ -610,15 +754,21 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
                      "unit": "T int32 lane-op/s", "frac": achieved / PEAK_INT_TOPS,
                      "traffic": traffic,
-                     "mixers_per_set": float(H[ok].mean()) if ok.any() else 0.0,
-                     "frac_one_pass": (float(ops1[ok].mean()) * n_sets / (ms * 1e-3) / 1e12 / PEAK_INT_TOPS
-                                       if ok.any() else 0.0),
+                     "work": "the GPU's own enumeration counts over the whole batch",
+                     "kernel_ms": kernel_ms,
+                     "mixers_per_set": float(H.mean()) if len(H) else 0.0,
+                     "counts_equal_oracle_sample": counts_equal,
+                     "frac_step": ops_launch / (ms * 1e-3) / 1e12 / PEAK_INT_TOPS,
+                     "frac_paper_schedule": (float(opsp[okp].mean()) * n_sets / (kernel_ms * 1e-3) / 1e12
+                                             / PEAK_INT_TOPS if okp.any() else 0.0),
+                     "mixers_per_set_paper_schedule": float(Hp[okp].mean()) if okp.any() else 0.0,
                      "lane_ops_per_mixer": c_mix,
-                     "hbm_gbs_algorithmic": hbm_bytes / (ms * 1e-3) / 1e9},
+                     "hbm_gbs_algorithmic": hbm_bytes / (kernel_ms * 1e-3) / 1e9},
         "cpu_baseline": {"value": got / t_cpu if t_cpu > 0 else None, "unit": "sets/s",
                          "cores": 1, "kind": "oracle",
                          "sample": f"every {stride}th set of the same batch, first {got} of them "
-                                   f"({t_cpu:.1f}s of single-thread CPU work)"},
+                                   f"({t_cpu:.1f}s of single-thread CPU work, the GPU's schedule)",
+                         "host": host, "all_cores": all_core, "other_configs": other_cfgs},
     }
     if args.copy_calibration > 0:
         nb = (args.copy_calibration // 16) * 16

@@ -11,9 +11,16 @@
  *  - Pointers marked "device" must be device memory of the context's GPU;
  *    the caller allocates, owns and frees every input and output buffer.  The
  *    context owns only its internal tables and scratch space.
- *  - Calls are asynchronous on the context's stream (dms_set_stream); argument
- *    errors are reported synchronously by the return value, per-set data
- *    problems by out_status.  dms_sync waits for the stream.
+ *  - Calls are asynchronous on the context's stream (dms_set_stream): they only
+ *    enqueue work, except that (a) the first call for a value of t copies that
+ *    t's specification tables to the device and waits for the copy, and (b) a
+ *    call needing more scratch space than the context holds waits for the
+ *    stream before replacing it.  Once an eager call of the same shape has run,
+ *    dms_sketch_csr, dms_lsh_keys and dms_bottomk therefore only enqueue
+ *    kernels and can be captured into a HIP graph.  Calls that say they
+ *    synchronize (index build, autotune, calibration, serving) do so always.
+ *    Argument errors are reported synchronously by the return value, per-set
+ *    data problems by out_status.  dms_sync waits for the stream.
  *  - A context is not thread safe; use one per host thread.
  *  - Return value: DMS_OK (0) or a negative DMS_E* code; dms_last_error gives
  *    the message of the last failure on that context.
@@ -38,7 +45,8 @@ typedef int32_t dms_status;
 #define DMS_SET_OK 0      /* sketch computed */
 #define DMS_SET_EMPTY 1   /* no positive weight: the minhash is undefined (J = 0/0) */
 #define DMS_SET_RANGE 2   /* largest weight outside [2^-768, 2^768], or phi beyond its cap */
-#define DMS_SET_INVALID 3 /* a negative, NaN or infinite weight */
+#define DMS_SET_INVALID 3 /* a negative, NaN or infinite weight; with DMS_FLAG_VALIDATE also a
+                             repeated element id */
 #define DMS_QUERY_OVERFLOW 4 /* dms_index_query: the query's buckets hold more than 2048 entries */
 
 /* Engines for the sketch and LSH calls (dms_set_option DMS_OPT_ENGINE). */
@@ -55,10 +63,9 @@ typedef int32_t dms_status;
                                wavefronts, one part of at most this many nonzeros each
                                (default 4096; 0 disables, and then every set must have fewer
                                than 2^32 nonzeros: queues name elements by 32-bit offsets within
-                               the set or part).  The call then reads two counts back
-                               from the device before its main launch; with 0, a sketch call only
-                               enqueues kernels and, once an eager call of the same size has sized
-                               the context's scratch, can be captured into a HIP graph. */
+                               the set or part).  The parts are planned on the device into
+                               scratch of fixed capacity (partial buckets of at most 256 MiB);
+                               a heavy set that no longer fits is sketched whole by one wave. */
 #define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
 #define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
                                Unlike the other options it changes the outputs: sketches made
@@ -68,17 +75,40 @@ typedef int32_t dms_status;
                                device before the main launch), 0 in input order.  Batches of
                                2^31 sets or more always run in input order. */
 
+#define DMS_OPT_TIMING 8    /* 1: bracket the main kernel of every dms_sketch_csr, dms_lsh_keys and
+                               dms_bottomk call with HIP events on the context's stream (read
+                               and reset by dms_kernel_time); 0 (default): no events */
+
 /* Hash functions (DMS_OPT_HASH). */
 #define DMS_HASH_MIX 0 /* SplitMix64's output function of (key XOR input) */
 #define DMS_HASH_TAB 1 /* simple tabulation of (key XOR input): XOR of one 64-bit word per input
                           byte, table b = MT19937-64 outputs 7 + 256 b .. 262 + 256 b for the seed
                           (the paper's randomness source, Section 4 "Implementation") */
 
+/* Flags of dms_sketch_csr, dms_lsh_keys and dms_bottomk. */
+#define DMS_FLAG_VALIDATE 1u /* a set listing an element id more than once gets DMS_SET_INVALID
+                                (without it, a repeated id behaves as one element of the larger
+                                weight: the same darts are met twice) */
+#define DMS_FLAG_COUNTERS 2u /* write the per-set enumeration counts to out_counters (must be
+                                non-NULL exactly when this flag is set): int64[n_sets*8] at
+                                [s*8 + q], q = 0 regions, 1 areas, 2 darts generated, 3 darts
+                                whose rank passed, 4 darts accepted (rank and weight), 5 phi
+                                passes run, 6 the last pass's phi (bit pattern of a double),
+                                7 zero.  Algorithm 1 visits the regions, areas and darts counted
+                                by 0..2.  The fast engine counts a retry pass's darts of 3 and 4
+                                only in its new rank band (tau_prev, tau] (it keeps the earlier
+                                ones), the plain engine every dart of rank <= tau.  All zero for a
+                                set whose row scan fails (empty, invalid, range). */
+
 /* Formats of dms_jaccard_est. */
 #define DMS_FMT_U32 0  /* k uint32 minhash values per set */
 #define DMS_FMT_1BIT 1 /* ceil(k/64) uint64 words per set, bit j at bit j%64 of word j/64 */
 
 typedef struct dms_ctx_s* dms_ctx;
+
+/* Version of the specification the sketches follow (constants, hash, float
+ * derivation); a database of sketches records it (dms_db_*). */
+#define DMS_SPEC_VERSION 1
 
 /* Create a context on HIP device `device`.  `seed` selects the hash functions:
  * the six 64-bit keys are the first six outputs of MT19937-64 seeded with it
@@ -92,7 +122,11 @@ dms_status dms_create(dms_ctx* out, int device, uint64_t seed);
 dms_status dms_destroy(dms_ctx ctx);
 
 /* Use `hip_stream` (a hipStream_t, or NULL for the null stream) for all later
- * calls on this context. */
+ * calls on this context.  The context's scratch is shared by its calls, so
+ * work queued on the new stream waits for what is queued on the old one (an
+ * event recorded on the old stream) -- except while either stream is being
+ * captured into a graph, when the caller orders the work (a capture cannot
+ * wait for work outside it).  Errors: DMS_EINVAL, DMS_EHIP. */
 dms_status dms_set_stream(dms_ctx ctx, void* hip_stream);
 
 /* Set / read one DMS_OPT_* option.  Errors: DMS_EINVAL for an unknown option
@@ -118,13 +152,16 @@ dms_status dms_get_option(dms_ctx ctx, int32_t option, double* value);
  *   out_status device int8[n_sets] or NULL: DMS_SET_*
  *   out_s    device uint64[n_sets*k] or NULL: the full 64-bit dart id hash
  *   out_rank device float64[n_sets*k] or NULL: the dart's rank (+inf if not OK)
- * Errors: DMS_EINVAL (k out of range, n_sets < 0, a required pointer NULL),
- * DMS_EHIP, DMS_ENOMEM.
+ *   flags    DMS_FLAG_* (0 for none)
+ *   out_counters device int64[n_sets*8] when flags has DMS_FLAG_COUNTERS, else NULL
+ * Errors: DMS_EINVAL (k out of range, n_sets < 0, a required pointer NULL,
+ * unknown flag bits, out_counters given without DMS_FLAG_COUNTERS or missing
+ * with it), DMS_EHIP, DMS_ENOMEM.
  */
 dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
                           const int32_t* idx, const double* w, int32_t k, uint32_t* out_u32,
                           uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                          double* out_rank);
+                          double* out_rank, uint32_t flags, int64_t* out_counters);
 
 /*
  * Autotuner for dms_sketch_csr: times the sketch of a prefix of the batch
@@ -152,11 +189,12 @@ dms_status dms_autotune(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, con
  *   L 1..1024, K 1..64, L*K <= 65536
  *   out_keys device uint64[n_sets*L] at [s*L + l]; 0 for a set not OK
  *   out_status device int8[n_sets] or NULL
+ *   flags, out_counters  as for dms_sketch_csr
  * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
  */
 dms_status dms_lsh_keys(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
                         const double* w, int32_t L, int32_t K, uint64_t* out_keys,
-                        int8_t* out_status);
+                        int8_t* out_status, uint32_t flags, int64_t* out_counters);
 
 /*
  * Weighted Jaccard estimates from sketches (Section 1.1): for pair p, with a
@@ -222,11 +260,13 @@ dms_status dms_index_destroy(dms_index ix);
  *   out_rank   device float64[n_sets*k] or NULL (+inf for such a set)
  *   out_status device int8[n_sets] or NULL
  *   k 1..1024
+ *   flags, out_counters  as for dms_sketch_csr (the rank and acceptance
+ *   counts are those of each pass's new rank band)
  * Errors: DMS_EINVAL, DMS_EHIP, DMS_ENOMEM.
  */
 dms_status dms_bottomk(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
                        const double* w, int32_t k, uint64_t* out_s, double* out_rank,
-                       int8_t* out_status);
+                       int8_t* out_status, uint32_t flags, int64_t* out_counters);
 
 /*
  * Jaccard estimate from two bottom-k sketches (dms_bottomk layout, both with
@@ -396,6 +436,13 @@ dms_status dms_server_submit(dms_server s, int32_t kind, int32_t k, int64_t nnz,
 dms_status dms_server_poll(dms_server s, int32_t wait_ms, int64_t max_out, int64_t* out_id,
                            int8_t* out_status, uint32_t* out_sketch, int64_t* out_ids, int32_t* out_dist,
                            double* out_latency_s, int64_t* n_out);
+
+/* Measurement support (DMS_OPT_TIMING): waits for the timed calls since the
+ * last dms_kernel_time and returns the summed duration of their main kernels
+ * (the persistent sketching kernel with its one-thread cursor reset, or the
+ * plain engine's kernel) in *out_ms and their number in *out_launches (may be
+ * NULL); then starts a new tally.  Errors: DMS_EINVAL, DMS_EHIP. */
+dms_status dms_kernel_time(dms_ctx ctx, double* out_ms, int64_t* out_launches);
 
 /* Wait until all work queued on the context's stream is done. */
 dms_status dms_sync(dms_ctx ctx);

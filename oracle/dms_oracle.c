@@ -44,6 +44,7 @@ typedef struct {
     double phi_max;            /* give up (status RANGE) beyond this */
     int32_t hash;              /* DMSO_HASH_*                      */
     uint64_t tab[8 * 256];     /* tabulation tables (DMSO_HASH_TAB) */
+    int32_t validate;          /* 1: a row listing an id twice is INVALID */
 } dmso_params;
 
 enum { DMSO_HASH_MIX = 0, DMSO_HASH_TAB = 1 };
@@ -207,12 +208,38 @@ static int darthash(const dmso_params* P, int64_t nnz, const int32_t* idx,
     return DMSO_OK;
 }
 
-/* Validate a row: DMSO_INVALID for a negative, NaN or infinite weight,
- * DMSO_EMPTY when no weight is positive, DMSO_RANGE when the largest weight is
- * outside [2^-768, 2^768].  On success *S is the sum of the positive weights in
- * row order. */
-static int check_row(int64_t nnz, const double* x, double* S)
+static int cmp_u32(const void* a, const void* b)
 {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+/* 1 if some id occurs twice in the row (ids compared as uint32), else 0;
+ * -1 when out of memory. */
+static int has_repeat(int64_t nnz, const int32_t* idx)
+{
+    if (nnz < 2) return 0;
+    uint32_t* c = (uint32_t*)malloc((size_t)nnz * sizeof(uint32_t));
+    if (!c) return -1;
+    for (int64_t e = 0; e < nnz; e++) c[e] = (uint32_t)idx[e];
+    qsort(c, (size_t)nnz, sizeof(uint32_t), cmp_u32);
+    int rep = 0;
+    for (int64_t e = 1; e < nnz && !rep; e++) rep = c[e] == c[e - 1];
+    free(c);
+    return rep;
+}
+
+/* Validate a row: DMSO_INVALID for a negative, NaN or infinite weight (and,
+ * when P->validate is set, for an id listed twice), DMSO_EMPTY when no weight
+ * is positive, DMSO_RANGE when the largest weight is outside [2^-768, 2^768].
+ * On success *S is the sum of the positive weights in row order. */
+static int check_row(const dmso_params* P, int64_t nnz, const int32_t* idx, const double* x, double* S)
+{
+    if (P->validate) {
+        int r = has_repeat(nnz, idx);
+        if (r < 0) return DMSO_NOMEM;
+        if (r) return DMSO_INVALID;
+    }
     double sum = 0.0, mx = 0.0;
     int any = 0;
     for (int64_t e = 0; e < nnz; e++) {
@@ -291,7 +318,7 @@ int dmso_minhash_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
                      dmso_counters* cnt)
 {
     double S;
-    int st = check_row(nnz, x, &S);
+    int st = check_row(P, nnz, idx, x, &S);
     if (st != DMSO_OK) return st;
     int filled = 0;
     double phi = P->phi0, tau_prev = -1.0;
@@ -383,7 +410,7 @@ int dmso_lsh_set(const dmso_params* P, int32_t L, int32_t K, int64_t nnz, const 
                  double* phi_final, dmso_counters* pass_cnt)
 {
     double S;
-    int st = check_row(nnz, x, &S);
+    int st = check_row(P, nnz, idx, x, &S);
     if (st != DMSO_OK) return st;
     size_t slots = (size_t)L * (size_t)K;
     uint64_t* bs = (uint64_t*)malloc(slots * sizeof(uint64_t));
@@ -485,7 +512,7 @@ int dmso_bottomk_set(const dmso_params* P, int32_t k, int64_t nnz, const int32_t
                      dmso_counters* cnt)
 {
     double S;
-    int st = check_row(nnz, x, &S);
+    int st = check_row(P, nnz, idx, x, &S);
     if (st != DMSO_OK) return st;
     double phi = P->phi0, tau_prev = -1.0;
     for (;;) {

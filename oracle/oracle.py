@@ -144,6 +144,7 @@ class Params(ctypes.Structure):
         ("phi_max", ctypes.c_double),
         ("hash", ctypes.c_int32),
         ("tab", ctypes.c_uint64 * TAB_WORDS),
+        ("validate", ctypes.c_int32),
     ]
 
 
@@ -227,9 +228,10 @@ def tab_tables(seed: int) -> tuple:
 
 
 def make_params(seed: int, t: int, phi0: float = 1.0, schedule: int = SCHED_PLUS_ONE,
-                phi_max: float = 2.0 ** 20, hash: int = HASH_MIX) -> Params:
+                phi_max: float = 2.0 ** 20, hash: int = HASH_MIX, validate: bool = False) -> Params:
     p = Params()
     p.hash = hash
+    p.validate = 1 if validate else 0
     if hash == HASH_TAB:
         for i, v in enumerate(tab_tables(seed)):
             p.tab[i] = v
@@ -296,14 +298,16 @@ def minhash_set(idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1
 
 
 def sketch_csr(row_ptr, idx, w, k: int, seed: int, t: int | None = None, phi0: float = 1.0,
-               schedule: int = SCHED_PLUS_ONE, full: bool = False, hash: int = HASH_MIX):
+               schedule: int = SCHED_PLUS_ONE, full: bool = False, hash: int = HASH_MIX,
+               validate: bool = False):
     """DartMinHash of every row of a CSR matrix.
 
     Returns dict with u32 [n,k], bits [n, ceil(k/64)] (uint64), status [n] (int8),
     and with ``full`` also s [n,k], rank [n,k], phi [n], counters [n] (every pass
-    summed) and counters_last [n] (the last pass)."""
+    summed) and counters_last [n] (the last pass).  With ``validate`` a row
+    listing an id twice gets status INVALID."""
     t = t_of_k(k) if t is None else t
-    P = make_params(seed, t, phi0, schedule, hash=hash)
+    P = make_params(seed, t, phi0, schedule, hash=hash, validate=validate)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
     n = len(row_ptr) - 1
     words = (k + 63) // 64
@@ -341,10 +345,11 @@ def lsh_set(idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
 
 
 def lsh_csr(row_ptr, idx, w, L: int, K: int, seed: int, phi0: float = 1.0,
-            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False):
+            schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False,
+            validate: bool = False):
     """(L,K) LSH keys of every row: dict keys [n,L] uint64, status [n] int8, and
     with ``counters`` the enumeration counts [n,2] (every pass summed, last pass)."""
-    P = make_params(seed, L * K, phi0, schedule, hash=hash)
+    P = make_params(seed, L * K, phi0, schedule, hash=hash, validate=validate)
     row_ptr, idx, w = _csr(row_ptr, idx, w)
     n = len(row_ptr) - 1
     keys = np.zeros((n, L), dtype=np.uint64)
@@ -376,13 +381,14 @@ def bottomk_set(idx, w, k: int, seed: int, phi0: float = 1.0, schedule: int = SC
 
 
 def bottomk_csr(row_ptr, idx, w, k: int, seed: int, phi0: float = 1.0,
-                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False):
+                schedule: int = SCHED_PLUS_ONE, hash: int = HASH_MIX, counters: bool = False,
+                validate: bool = False):
     """Bottom-k sketches of every row: dict s [n,k] uint64, rank [n,k] float64,
     u32 [n,k] (low 32 bits of s), status [n] int8, and with ``counters`` the
     enumeration counts [n,2] (every pass summed, last pass)."""
     rp, idx, w = _csr(row_ptr, idx, w)
     n = len(rp) - 1
-    P = make_params(seed, k, phi0, schedule, hash=hash)
+    P = make_params(seed, k, phi0, schedule, hash=hash, validate=validate)
     s = np.zeros((n, k), dtype=np.uint64)
     r = np.zeros((n, k), dtype=np.float64)
     st = np.zeros(n, dtype=np.int8)

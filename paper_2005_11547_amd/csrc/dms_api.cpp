@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "../../include/dms.h"
 #include "dms_internal.h"
@@ -18,6 +19,7 @@ struct dms_ctx_s {
     int device = 0;
     uint64_t seed = 0;
     hipStream_t stream = nullptr;
+    hipEvent_t switch_event = nullptr;  // orders work across dms_set_stream
     int engine = DMS_ENGINE_FAST;
     int n_cu = 0;
     unsigned long long* counter = nullptr;  // work-stealing cursor of the fast engine
@@ -31,6 +33,10 @@ struct dms_ctx_s {
     size_t heavy_bytes = 0;
     uint64_t* partial = nullptr;
     size_t partial_bytes = 0;
+    void* planned = nullptr;                 // per set: served by parts of the device plan
+    size_t planned_bytes = 0;
+    void* repeated = nullptr;                // per set: repeated ids (DMS_FLAG_VALIDATE)
+    size_t repeated_bytes = 0;
     // first phi of the minhash schedule: at 1.3 a second pass is needed with
     // probability about k^(1-phi) e^(-phi) (0.07 at k = 256), which costs less
     // than the larger first pass saves (Theorem 1's retry argument)
@@ -44,6 +50,11 @@ struct dms_ctx_s {
     double phi_max = 1048576.0;
     std::map<uint32_t, dms::SpecTables*> spec;  // device copies, keyed by t
     std::string err;
+    // DMS_OPT_TIMING: event pairs around the main kernel of each sketching
+    // call since the last dms_kernel_time (the pool is reused)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+    size_t n_timed = 0;
 };
 
 namespace {
@@ -95,11 +106,16 @@ dms_status spec_for(dms_ctx c, uint32_t t, const dms::SpecTables** out)
 }
 
 // Make *buf hold at least `need` bytes of device memory (contents not kept).
-// The stream has been synchronised by the caller.
+// Replacing a buffer first waits for the stream, whose queued work may still
+// use the old one.
 dms_status grow(dms_ctx c, void** buf, size_t* have, size_t need)
 {
     if (need <= *have) return DMS_OK;
-    if (*buf) (void)hipFree(*buf);
+    if (*buf) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+        (void)hipFree(*buf);
+    }
     *buf = nullptr;
     *have = 0;
     const size_t bytes = need + need / 4 + 256;
@@ -131,18 +147,64 @@ dms_status size_order(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const u
     *order = nullptr;
     if (!c->order || n_sets < 2 || n_sets >= ((int64_t)1 << 31)) return DMS_OK;
     const size_t need = dms::size_order_bytes(n_sets);
-    if (need > c->order_bytes) {
-        if (c->order_buf) (void)hipFree(c->order_buf);
-        c->order_buf = nullptr;
-        c->order_bytes = 0;
-        hipError_t e = hipMalloc(&c->order_buf, need);
-        if (e != hipSuccess) return fail(c, DMS_ENOMEM, "hipMalloc(%zu bytes of order scratch): %s", need, hipGetErrorString(e));
-        c->order_bytes = need;
-    }
+    if (dms_status g = grow(c, &c->order_buf, &c->order_bytes, need); g != DMS_OK) return g;
     hipError_t e = dms::launch_size_order(n_sets, row_ptr, c->order_buf, c->order_bytes, order, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "size order");
     return DMS_OK;
 }
+
+// Checks flags and out_counters of a sketching call and, for DMS_FLAG_VALIDATE,
+// flags the rows whose ids repeat; fills the launch extras.
+dms_status prepare_extras(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                          uint32_t flags, int64_t* out_counters, dms::LaunchExtras* x)
+{
+    if (flags & ~(uint32_t)(DMS_FLAG_VALIDATE | DMS_FLAG_COUNTERS))
+        return fail(c, DMS_EINVAL, "unknown flag bits 0x%x", flags);
+    if (((flags & DMS_FLAG_COUNTERS) != 0) != (out_counters != nullptr))
+        return fail(c, DMS_EINVAL, "out_counters must be given exactly when DMS_FLAG_COUNTERS is set");
+    x->counters = out_counters;
+    x->repeated = nullptr;
+    if (flags & DMS_FLAG_VALIDATE) {
+        if (dms_status g = grow(c, &c->repeated, &c->repeated_bytes, (size_t)n_sets); g != DMS_OK) return g;
+        hipError_t e = dms::launch_repeated_ids(n_sets, row_ptr, idx, (uint8_t*)c->repeated, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "row validation");
+        x->repeated = (const uint8_t*)c->repeated;
+    }
+    return DMS_OK;
+}
+
+// Parts a device plan may hold for k buckets: their partial buckets take at
+// most 256 MiB (sets beyond the capacity are sketched whole).
+int64_t plan_capacity(int32_t k)
+{
+    int64_t cap = ((int64_t)256 << 20) / (16 * (int64_t)k);
+    return cap < 64 ? 64 : (cap > ((int64_t)1 << 20) ? ((int64_t)1 << 20) : cap);
+}
+
+// Brackets the main kernel of a sketching call with events (DMS_OPT_TIMING).
+struct KernelTimer {
+    dms_ctx c;
+    bool on = false;
+    explicit KernelTimer(dms_ctx ctx) : c(ctx)
+    {
+        if (!c->timing) return;
+        if (c->n_timed == c->timed.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            c->timed.emplace_back(a, b);
+        }
+        on = hipEventRecord(c->timed[c->n_timed].first, c->stream) == hipSuccess;
+    }
+    void done()
+    {
+        if (on && hipEventRecord(c->timed[c->n_timed].second, c->stream) == hipSuccess) ++c->n_timed;
+        on = false;
+    }
+};
 
 struct DeviceGuard {
     int prev = -1;
@@ -185,7 +247,10 @@ dms_status dms_create(dms_ctx* out, int device, uint64_t seed)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
         hipMalloc((void**)&c->counter, 64) != hipSuccess ||
-        hipMalloc((void**)&c->plan, 64) != hipSuccess) {
+        hipMalloc((void**)&c->plan, 64) != hipSuccess ||
+        hipEventCreateWithFlags(&c->switch_event, hipEventDisableTiming) != hipSuccess) {
+        if (c->counter) (void)hipFree(c->counter);
+        if (c->plan) (void)hipFree(c->plan);
         delete c;
         return DMS_EHIP;
     }
@@ -206,6 +271,13 @@ dms_status dms_destroy(dms_ctx c)
     if (c->heavy) (void)hipFree(c->heavy);
     if (c->partial) (void)hipFree(c->partial);
     if (c->order_buf) (void)hipFree(c->order_buf);
+    if (c->planned) (void)hipFree(c->planned);
+    if (c->repeated) (void)hipFree(c->repeated);
+    if (c->switch_event) (void)hipEventDestroy(c->switch_event);
+    for (auto& pr : c->timed) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     delete c;
     return DMS_OK;
 }
@@ -213,7 +285,25 @@ dms_status dms_destroy(dms_ctx c)
 dms_status dms_set_stream(dms_ctx c, void* s)
 {
     if (!c) return DMS_EINVAL;
-    c->stream = (hipStream_t)s;
+    hipStream_t next = (hipStream_t)s;
+    if (next == c->stream) return DMS_OK;
+    // The context's scratch (work cursor, plan, size order) is shared by its
+    // calls: work queued on the new stream starts after the old stream's.  A
+    // stream being captured into a graph cannot wait for work outside the
+    // capture; then the switch adds no ordering.
+    DeviceGuard g(c->device);
+    // The new stream is asked first: while it captures, the old one (often the
+    // null stream, which must not be touched during a capture) is left alone.
+    hipStreamCaptureStatus a = hipStreamCaptureStatusActive, b = hipStreamCaptureStatusActive;
+    bool plain = hipStreamIsCapturing(next, &b) == hipSuccess && b == hipStreamCaptureStatusNone;
+    plain = plain && hipStreamIsCapturing(c->stream, &a) == hipSuccess && a == hipStreamCaptureStatusNone;
+    (void)hipGetLastError();  // a refused capture query leaves no error behind
+    if (plain) {
+        hipError_t e = hipEventRecord(c->switch_event, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(next, c->switch_event, 0);
+        if (e != hipSuccess) return hip_fail(c, e, "stream switch");
+    }
+    c->stream = next;
     return DMS_OK;
 }
 
@@ -233,6 +323,10 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
     case DMS_OPT_ORDER:
         if (v != 0.0 && v != 1.0) return fail(c, DMS_EINVAL, "order must be 0 or 1");
         c->order = (int)v;
+        return DMS_OK;
+    case DMS_OPT_TIMING:
+        if (v != 0.0 && v != 1.0) return fail(c, DMS_EINVAL, "timing must be 0 or 1");
+        c->timing = v != 0.0;
         return DMS_OK;
     case DMS_OPT_SPLIT_NNZ:
         if (!(v >= 0.0) || v > 1e12 || v != (double)(int64_t)v)
@@ -266,13 +360,15 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_SPLIT_NNZ: *v = c->split_nnz; return DMS_OK;
     case DMS_OPT_HASH: *v = c->hash; return DMS_OK;
     case DMS_OPT_ORDER: *v = c->order; return DMS_OK;
+    case DMS_OPT_TIMING: *v = c->timing ? 1.0 : 0.0; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
     }
 }
 
 dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
                           const double* w, int32_t k, uint32_t* out_u32, uint64_t* out_bits,
-                          int8_t* out_status, uint64_t* out_s, double* out_rank)
+                          int8_t* out_status, uint64_t* out_s, double* out_rank, uint32_t flags,
+                          int64_t* out_counters)
 {
     if (!c) return DMS_EINVAL;
     c->err.clear();
@@ -284,49 +380,52 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     const dms::SpecTables* sp = nullptr;
     dms_status st = spec_for(c, dms::t_of_k(k), &sp);
     if (st != DMS_OK) return st;
+    dms::LaunchExtras x;
+    if ((st = prepare_extras(c, n_sets, row_ptr, idx, flags, out_counters, &x)) != DMS_OK) return st;
     hipError_t e;
     // the flattened engine keeps its queues and k buckets in one block's LDS;
     // beyond 64 KiB the plain engine serves the call
     if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeMinhash, k, 1, 1) > 65536) {
+        KernelTimer tm(c);
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
-                                     out_status, out_s, out_rank, c->phi0, c->phi_max, c->hash, c->stream);
+                                     out_status, out_s, out_rank, c->phi0, c->phi_max, c->hash, x, c->stream);
+        tm.done();
     } else {
         const int64_t split = (int64_t)c->split_nnz;
-        int64_t n_parts = 0;
+        int64_t part_cap = 0;
         if (split > 0) {
-            // count the parts of the sets above the threshold, size the scratch, fill the plan
-            unsigned long long counts[2] = {0, 0};
-            e = dms::launch_plan_count(n_sets, row_ptr, split, c->plan, c->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(counts, c->plan, sizeof counts, hipMemcpyDeviceToHost, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            // the heavy sets are planned on the device into scratch of a fixed
+            // capacity, so the call only enqueues kernels
+            part_cap = plan_capacity(k);
+            dms_status g2 = grow(c, &c->parts, &c->parts_bytes, (size_t)part_cap * dms::plan_part_bytes());
+            if (g2 == DMS_OK)
+                g2 = grow(c, &c->heavy, &c->heavy_bytes, (size_t)(part_cap / 2) * dms::plan_heavy_bytes());
+            if (g2 == DMS_OK)
+                g2 = grow(c, (void**)&c->partial, &c->partial_bytes, (size_t)part_cap * 16 * (size_t)k);
+            if (g2 == DMS_OK) g2 = grow(c, &c->planned, &c->planned_bytes, (size_t)n_sets);
+            if (g2 != DMS_OK) return g2;
+            e = dms::launch_plan(n_sets, row_ptr, w, split, part_cap, c->plan, c->parts, c->heavy,
+                                 (uint8_t*)c->planned, out_counters, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "sketch planning");
-            const int64_t n_heavy = (int64_t)counts[0];
-            n_parts = (int64_t)counts[1];
-            if (n_parts > 0) {
-                dms_status g2 = grow(c, &c->parts, &c->parts_bytes, (size_t)n_parts * dms::plan_part_bytes());
-                if (g2 == DMS_OK) g2 = grow(c, &c->heavy, &c->heavy_bytes, (size_t)n_heavy * dms::plan_heavy_bytes());
-                if (g2 == DMS_OK)
-                    g2 = grow(c, (void**)&c->partial, &c->partial_bytes, (size_t)n_parts * 16 * (size_t)k);
-                if (g2 != DMS_OK) return g2;
-                e = dms::launch_plan_fill(n_sets, row_ptr, w, split, n_heavy, c->plan, c->parts,
-                                          c->heavy, c->stream);
-                if (e != hipSuccess) return hip_fail(c, e, "sketch planning");
-            }
         }
         const uint32_t* order = nullptr;
         if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
+        KernelTimer tm(c);
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
                                           c->counter, resident_blocks(c, dms::kModeMinhash, k, 1), c->parts,
-                                          n_parts, c->heavy, c->partial, split, order, c->hash, c->stream);
+                                          part_cap, c->heavy, c->partial, split, order, c->hash, x,
+                                          split > 0 ? c->plan : nullptr,
+                                          split > 0 ? (const uint8_t*)c->planned : nullptr, c->stream);
+        tm.done();
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
     return DMS_OK;
 }
 
 dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
-                       const double* w, int32_t k, uint64_t* out_s, double* out_rank, int8_t* out_status)
+                       const double* w, int32_t k, uint64_t* out_s, double* out_rank, int8_t* out_status,
+                       uint32_t flags, int64_t* out_counters)
 {
     if (!c) return DMS_EINVAL;
     c->err.clear();
@@ -338,14 +437,18 @@ dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const 
     const dms::SpecTables* sp = nullptr;
     dms_status st = spec_for(c, (uint32_t)k, &sp);  // t = k
     if (st != DMS_OK) return st;
+    dms::LaunchExtras x;
+    if ((st = prepare_extras(c, n_sets, row_ptr, idx, flags, out_counters, &x)) != DMS_OK) return st;
     // phi0 = 1 + 4/sqrt(k) finds k darts in the first pass but for a 4-sigma shortfall
     const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 4.0 / std::sqrt((double)k);
     const uint32_t* order = nullptr;
     if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
+    KernelTimer tm(c);
     hipError_t e = dms::launch_bottomk_fast(sp, n_sets, row_ptr, idx, w, k, out_s, out_rank, out_status,
                                             phi0, c->phi_max, c->counter,
-                                            resident_blocks(c, dms::kModeBottomK, k, 1), order, c->hash,
+                                            resident_blocks(c, dms::kModeBottomK, k, 1), order, c->hash, x,
                                             c->stream);
+    tm.done();
     if (e != hipSuccess) return hip_fail(c, e, "bottom-k launch");
     return DMS_OK;
 }
@@ -366,7 +469,7 @@ dms_status dms_jaccard_est_bottomk(dms_ctx c, int64_t n_pairs, const double* ran
 
 dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
                         const double* w, int32_t L, int32_t K, uint64_t* out_keys,
-                        int8_t* out_status)
+                        int8_t* out_status, uint32_t flags, int64_t* out_counters)
 {
     if (!c) return DMS_EINVAL;
     c->err.clear();
@@ -381,16 +484,22 @@ dms_status dms_lsh_keys(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     const dms::SpecTables* sp = nullptr;
     dms_status st = spec_for(c, (uint32_t)(L * K), &sp);
     if (st != DMS_OK) return st;
+    dms::LaunchExtras x;
+    if ((st = prepare_extras(c, n_sets, row_ptr, idx, flags, out_counters, &x)) != DMS_OK) return st;
     hipError_t e;
     if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeLsh, L, K, 1) > 65536) {
+        KernelTimer tm(c);
         e = dms::launch_lsh_plain(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
-                                  c->lsh_phi0, c->phi_max, c->hash, c->stream);
+                                  c->lsh_phi0, c->phi_max, c->hash, x, c->stream);
+        tm.done();
     } else {
         const uint32_t* order = nullptr;
         if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
+        KernelTimer tm(c);
         e = dms::launch_lsh_fast(sp, n_sets, row_ptr, idx, w, L, K, out_keys, out_status,
                                  c->lsh_phi0, c->phi_max, c->counter, resident_blocks(c, dms::lsh_fast_mode(L, K), L, K),
-                                 order, c->hash, c->stream);
+                                 order, c->hash, x, c->stream);
+        tm.done();
     }
     if (e != hipSuccess) return hip_fail(c, e, "lsh launch");
     return DMS_OK;
@@ -510,6 +619,27 @@ dms_status dms_calibrate(dms_ctx c, int32_t kind, int32_t iters, int64_t bytes, 
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(c, e, "calibration");
     *out_ms = ms;
+    return DMS_OK;
+}
+
+dms_status dms_kernel_time(dms_ctx c, double* out_ms, int64_t* out_launches)
+{
+    if (!c || !out_ms) return DMS_EINVAL;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    double total = 0.0;
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < c->n_timed && e == hipSuccess; ++i) {
+        e = hipEventSynchronize(c->timed[i].second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->timed[i].first, c->timed[i].second);
+        total += ms;
+    }
+    const int64_t n = (int64_t)c->n_timed;
+    c->n_timed = 0;
+    if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
+    *out_ms = total;
+    if (out_launches) *out_launches = n;
     return DMS_OK;
 }
 
@@ -657,7 +787,7 @@ dms_status dms_index_build(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, co
         // classes and normalised weights, then the (L,K) keys of the normalised sets
         e = dms::launch_index_prep(n_sets, row_ptr, idx, w, wn, ix->cls, ix->status, st);
         if (e != hipSuccess) rc = hip_fail(c, e, "index prep");
-        if (rc == DMS_OK) rc = dms_lsh_keys(c, n_sets, row_ptr, idx, wn, L, K, keys, kst);
+        if (rc == DMS_OK) rc = dms_lsh_keys(c, n_sets, row_ptr, idx, wn, L, K, keys, kst, 0, nullptr);
         if (rc == DMS_OK) {
             e = dms::launch_index_order(n_sets, ix->cls, ix->status, okey, okey2, ord, n_ok_dev, scratch,
                                         scratch_bytes, st);
@@ -753,7 +883,7 @@ dms_status dms_index_query(dms_index ix, int64_t n_q, const int64_t* q_row_ptr, 
     int8_t* qst = (int8_t*)(b + o_qs);
     e = dms::launch_query_prep(n_q, q_row_ptr, q_idx, q_w, span, xrp, xidx, xw, qcls, qst, st);
     if (e != hipSuccess) return hip_fail(c, e, "query prep");
-    dms_status rc = dms_lsh_keys(c, (int64_t)rows, xrp, xidx, xw, ix->L, ix->K, qkeys, xst);
+    dms_status rc = dms_lsh_keys(c, (int64_t)rows, xrp, xidx, xw, ix->L, ix->K, qkeys, xst, 0, nullptr);
     if (rc != DMS_OK) return rc;
     e = dms::launch_index_query(n_q, span, ix->L, qkeys, xst, qcls, qst, ix->tkeys, ix->tvals, ix->n_ok,
                                 q_row_ptr, q_idx, q_w, ix->rp, ix->idx, ix->w, j1, topn, out_ids, out_j,
@@ -801,7 +931,7 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         for (int r = 0; r < 3 && rc == DMS_OK; ++r) {
             hipError_t x = hipEventRecord(e0, c->stream);
             if (x != hipSuccess) { rc = hip_fail(c, x, "autotune event"); break; }
-            rc = dms_sketch_csr(c, n, row_ptr, idx, w, k, out, nullptr, st, nullptr, nullptr);
+            rc = dms_sketch_csr(c, n, row_ptr, idx, w, k, out, nullptr, st, nullptr, nullptr, 0, nullptr);
             if (rc != DMS_OK) break;
             x = hipEventRecord(e1, c->stream);
             if (x == hipSuccess) x = hipEventSynchronize(e1);

@@ -63,6 +63,24 @@ __device__ __forceinline__ double r_corner(const double* tab, int rho)
     return rho < kTable ? tab[rho] : ldexp(1.0, rho);
 }
 
+// Length of the prefix of c in [0, cap) with base + c * step <= bound, for an
+// exit predicate that holds at c = 0 and, with rounding monotone, stays false
+// once false: the columns of a region under x_i, or its rows below tau
+// (Section 2).  `est` is a real-number estimate of the answer; it is clamped to
+// [1, cap] and corrected one step at a time with the exact predicate.  Counts of
+// 2^52 or more are returned unrefined (the callers reject everything above 2^32).
+__device__ __forceinline__ double prefix_count(double base, double step, double bound, double cap,
+                                               double est)
+{
+    double c = est;
+    if (!(c >= 1.0)) c = 1.0;
+    if (c > cap) c = cap;
+    if (c >= 0x1.0p52) return c;
+    while (c < cap && base + c * step <= bound) c += 1.0;
+    while (c > 1.0 && !(base + (c - 1.0) * step <= bound)) c -= 1.0;
+    return c;
+}
+
 // bucket = (hi32(s) * n) >> 32
 __device__ __forceinline__ uint32_t bucket_of(uint64_t s, uint32_t n)
 {

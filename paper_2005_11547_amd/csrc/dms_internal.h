@@ -66,6 +66,12 @@ struct Part {
     int32_t index;   // part number within the set
 };
 
+// Per-set enumeration counts (DMS_FLAG_COUNTERS): regions, areas, darts
+// generated, darts whose rank lies in the pass's new band (tau_prev, tau],
+// those of them accepted, phi passes run, the last phi (bit pattern of the
+// double), and a zero word.
+constexpr int kCounterWords = 8;
+
 // Per-set status values written to out_status.
 enum SetStatus : int8_t { kSetOk = 0, kSetEmpty = 1, kSetRange = 2, kSetInvalid = 3, kQueryOverflow = 4 };
 

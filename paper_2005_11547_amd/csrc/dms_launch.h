@@ -11,18 +11,29 @@
 #include "dms_internal.h"
 
 namespace dms {
+// Optional outputs and checks of a sketching launch (DMS_FLAG_*): per-set
+// enumeration counts (kCounterWords int64 per set) and per-set flags of rows
+// whose element ids repeat (those sets get DMS_SET_INVALID).
+struct LaunchExtras {
+    int64_t* counters = nullptr;
+    const uint8_t* repeated = nullptr;
+};
+
 hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                                const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                                uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
-                               double* out_rank, double phi0, double phi_max, int hash, hipStream_t st);
+                               double* out_rank, double phi0, double phi_max, int hash,
+                               const LaunchExtras& x, hipStream_t st);
 hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                             const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
-                            int8_t* out_status, double phi0, double phi_max, int hash, hipStream_t st);
+                            int8_t* out_status, double phi0, double phi_max, int hash,
+                            const LaunchExtras& x, hipStream_t st);
 hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, int hash, hipStream_t st);
+                              unsigned long long* counter, int blocks, int hash, const LaunchExtras& x,
+                              hipStream_t st);
 int fast_waves(int mode, int k, int K);
 int fast_blocks_per_cu(int mode, int k, int K, int waves);
 size_t fast_lds(int mode, int k, int K, int waves);
@@ -33,7 +44,7 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,
                                unsigned long long* counter, int blocks, const uint32_t* order, int hash,
-                               hipStream_t st);
+                               const LaunchExtras& x, hipStream_t st);
 hipError_t launch_bottomk_jaccard(int64_t n_pairs, const double* ra, const uint64_t* sa, const double* rb,
                                   const uint64_t* sb, int k, double* out, hipStream_t st);
 hipError_t launch_index_prep(int64_t n, const int64_t* rp, const int32_t* idx, const double* w, double* wn,
@@ -60,19 +71,22 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    const uint32_t* order, int hash, hipStream_t st);
+                                    const uint32_t* order, int hash, const LaunchExtras& x,
+                                    const unsigned long long* plan_dev, const uint8_t* planned, hipStream_t st);
 size_t plan_part_bytes();
 size_t plan_heavy_bytes();
-hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
-                             unsigned long long* plan, hipStream_t st);
-hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
-                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
-                            hipStream_t st);
+// Device-side plan of the heavy sets for launch_sketch_fast_split: resets
+// plan[0..7], writes at most part_cap parts (plan[1] of them, for plan[0] heavy
+// sets), their row scans, and planned[n_sets] (1 for a set served by parts);
+// zeroes the counters of planned sets when out_cnt is given.
+hipError_t launch_plan(int64_t n_sets, const int64_t* rp, const double* w, int64_t split, int64_t part_cap,
+                       unsigned long long* plan, void* parts, void* heavy, uint8_t* planned, int64_t* out_cnt,
+                       hipStream_t st);
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
                            unsigned long long* counter, int blocks, const uint32_t* order, int hash,
-                           hipStream_t st);
+                           const LaunchExtras& x, hipStream_t st);
 size_t hamming_partial_bytes(int64_t n_q, int n_blocks, int topk);
 int hamming_blocks(int64_t n_db, int n_cu);
 hipError_t launch_hamming(const uint64_t* db, int64_t n_db, int words, const uint64_t* queries,
@@ -92,6 +106,9 @@ size_t fast_lds_bytes(int k, int waves);
 hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
                              hipStream_t st);
 size_t size_order_bytes(int64_t n_sets);
+// Per-set flags (1 = some element id occurs twice in the row) for DMS_FLAG_VALIDATE.
+hipError_t launch_repeated_ids(int64_t n_sets, const int64_t* rp, const int32_t* idx, uint8_t* out,
+                               hipStream_t st);
 hipError_t launch_size_order(int64_t n_sets, const int64_t* rp, void* scratch, size_t scratch_bytes,
                              const uint32_t** order, hipStream_t st);
 

@@ -235,14 +235,15 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
                                                   s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
                                                   dms::ctx_phi_max(S->ctx), s.d_counter + g,
                                                   2 * dms::ctx_n_cu(S->ctx), dp, n_parts, dh, db,
-                                                  n_parts > 0 ? split : 0, nullptr, dms::ctx_hash(S->ctx), st);
+                                                  n_parts > 0 ? split : 0, nullptr, dms::ctx_hash(S->ctx),
+                                                  dms::LaunchExtras{}, nullptr, nullptr, st);
             part_base += n_parts;
             part_heavy += n_heavy;
             bucket_base += n_parts * 2 * (int64_t)k;
         } else {
             e = dms::launch_sketch_plain(sp, n, s.d_rp + row0, s.d_idx, s.d_w, k, o32, obits,
                                          s.d_status + row0, nullptr, nullptr, dms::ctx_phi0(S->ctx),
-                                         dms::ctx_phi_max(S->ctx), dms::ctx_hash(S->ctx), st);
+                                         dms::ctx_phi_max(S->ctx), dms::ctx_hash(S->ctx), dms::LaunchExtras{}, st);
         }
         row0 += n;
     }
@@ -398,6 +399,7 @@ dms_status dms_server_replay(dms_server S, int64_t n_req, const double* arrival_
             s.busy = false;
             progress = true;
         }
+        if (status != DMS_OK) break;  // a failed slot: launch nothing more
         // admission into a free slot, in arrival order, within the slot's memory
         if (!pending.empty()) {
             for (Slot& s : S->slots) {

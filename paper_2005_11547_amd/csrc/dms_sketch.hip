@@ -21,10 +21,10 @@
 //                  id hash and enter the bucket minima.
 //
 // Column and row counts of a region come from a closed form corrected with the
-// exact loop-exit predicate, so the visited areas are exactly those of
-// Algorithm 1's loops with their early exits (the plain kernel in
-// dms_plain.hip walks those loops literally).
+// exact loop-exit predicate (prefix_count), so the visited areas are exactly
+// those of Algorithm 1's loops with their early exits.
 #include "dms_device.h"
+#include "dms_launch.h"
 
 namespace dms {
 
@@ -273,19 +273,6 @@ __device__ __forceinline__ T& at(unsigned char* base, uint32_t off, uint32_t i)
     return reinterpret_cast<T*>(base + off)[i];
 }
 
-// Number of c in [0, cap) with base + c * step <= bound (an exit predicate
-// that is monotone in c and true at c = 0), starting from the estimate est.
-__device__ __forceinline__ double exact_count(double base, double step, double bound, double cap,
-                                              double est)
-{
-    double c = est;
-    if (!(c >= 1.0)) c = 1.0;
-    if (c > cap) c = cap;
-    while (c < cap && base + c * step <= bound) c += 1.0;
-    while (c > 1.0 && !(base + (c - 1.0) * step <= bound)) c -= 1.0;
-    return c;
-}
-
 }  // namespace
 
 // Persistent flattened DartHash with one of three sinks: DartMinHash (k
@@ -299,7 +286,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             uint32_t* out_u32, uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
             double* out_rank, uint64_t* out_keys, double phi0, double phi_max,
             unsigned long long* next_set, const Part* __restrict__ parts, int64_t n_parts,
-            HeavySet* heavy, uint64_t* partial, int64_t split, const uint32_t* __restrict__ order)
+            HeavySet* heavy, uint64_t* partial, int64_t split, const uint32_t* __restrict__ order,
+            int64_t* out_cnt, const uint8_t* __restrict__ repeated, const unsigned long long* plan_dev,
+            const uint8_t* __restrict__ planned)
 {
     constexpr bool RT = MODE == kModeLshReg;  // K = 8 tables in registers, one per lane
     constexpr bool LSH = MODE == kModeLsh || RT;
@@ -471,6 +460,12 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         wave_sync();
     };
 
+    // Enumeration counts of the current set or part (wave-uniform): regions,
+    // areas, darts generated, darts with rank in (tau_prev, tau], those of them
+    // accepted, and phi passes run; phi_end is the last pass's phi.
+    uint64_t n_reg = 0, n_area = 0, n_gen = 0, n_rank = 0, n_acc = 0, n_pass = 0;
+    double phi_end = 0.0;
+
     // Runs phi passes over the elements [lo, hi) of a row with ||x||_1 = S,
     // starting at phi (darts of rank <= tau_prev are already in the buckets),
     // until no bucket is empty -- or just one pass when `single`.  Returns the
@@ -480,6 +475,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             for (;;) {
                 if (phi > phi_max) { status = kSetRange; break; }
                 const double tau = phi / S;
+                n_pass += 1;
+                phi_end = phi;
                 // rho runs over 0 .. B1-1: the rows whose lower corner is <= tau
                 int B1 = 0;
                 while (B1 < kMaxIndex && r_corner(sR, B1) <= tau) ++B1;
@@ -551,6 +548,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     const bool more = has && X > 1;
                     const uint64_t bp = __ballot(pass);
                     const uint64_t bm = __ballot(more);
+                    n_gen += (uint64_t)__popcll(__ballot(has));
+                    n_rank += (uint64_t)__popcll(bp);
                     if (pass) {
                         const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
                         at<uint64_t>(wb, kOffPqA, pos) = a;
@@ -588,6 +587,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const double V = unit53(H(a ^ KV ^ j));
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
+                        n_acc += (uint64_t)__popcll(__ballot(acc));
                         uint64_t s = 0;
                         if (acc) s = H(a ^ KS ^ j);
                         if (RT) {
@@ -663,6 +663,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const bool more = act && j + 1 < X;
                         const uint64_t bp = __ballot(pass);
                         const uint64_t bm = __ballot(more);
+                        n_gen += m;
+                        n_rank += (uint64_t)__popcll(bp);
                         wave_sync();  // every entry of the round is read before any write
                         if (pass) {
                             const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
@@ -733,6 +735,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = poisson_head(C, a);
                         }
+                        n_area += m;
                         emit_area(act, a, ei, rv, wv, meta, X, false);
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
@@ -750,6 +753,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         // ---------------- region round ----------------
                         const uint32_t left = chunk_total - reg_done;
                         const uint32_t m = left < 64 ? left : 64;
+                        n_reg += m;
+                        n_area += m;  // every region's first area (w = r = 0)
                         at<int32_t>(wb, kOffMark, lane) = 0;
                         wave_sync();
                         if (nreg > 0 && nreg_excl + nreg > reg_done && nreg_excl < reg_done + 64)
@@ -803,10 +808,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                     const double dnu = ldexp(u, (int)nu - (int)rho);
                                     const double drho = ldexp(1.0, (int)rho - (int)nu);
                                     const double wcap = ldexp(1.0, (int)rho);
-                                    wc = exact_count(Wn, dnu, x, wcap,
+                                    wc = prefix_count(Wn, dnu, x, wcap,
                                                      floor((x - Wn) * td * ldexp(1.0, (int)rho - (int)nu)) + 1.0);
                                     const double rcap = ldexp(1.0, (int)nu);
-                                    rcn = exact_count(Rr, drho, tau, rcap,
+                                    rcn = prefix_count(Rr, drho, tau, rcap,
                                                       floor((tau - Rr) * ldexp(1.0, (int)nu - (int)rho)) + 1.0);
                                 }
                                 const double nad = wc * rcn;
@@ -891,14 +896,18 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         }
     };
 
+    // parts of a device plan: their count was written by the planning kernel
+    const int64_t np = plan_dev ? (int64_t)plan_dev[1] : n_parts;
     for (;;) {
         unsigned long long got = 0;
         if (lane == 0) got = atomicAdd(next_set, 1ull);
         const int64_t item = (int64_t)__shfl(got, 0, kWave);
-        if (item >= n_parts + n_sets) break;
+        if (item >= np + n_sets) break;
         int64_t set;
         int8_t status;
-        if (MODE == kModeMinhash && item < n_parts) {
+        n_reg = n_area = n_gen = n_rank = n_acc = n_pass = 0;
+        phi_end = 0.0;
+        if (MODE == kModeMinhash && item < np) {
             // ---- one part of a heavy set ----
             const Part pt = parts[item];
             HeavySet* hs = heavy + pt.heavy;
@@ -908,6 +917,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             const int64_t hi = lo + split < b1 ? lo + split : b1;
             const double S = hs->sum;
             status = (int8_t)hs->status;
+            if (status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
             uint64_t* mine = partial + (size_t)(hs->base + pt.index) * 2 * k;
             if (status == kSetOk) {
                 clear_buckets();
@@ -918,6 +928,18 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     mine[k + j] = bin_s[j];
                 }
             }
+            if (out_cnt && lane == 0) {
+                // the part's share of the set's counts (the plan zeroed them)
+                int64_t* oc = out_cnt + set * kCounterWords;
+                atomicAdd((unsigned long long*)&oc[0], (unsigned long long)n_reg);
+                atomicAdd((unsigned long long*)&oc[1], (unsigned long long)n_area);
+                atomicAdd((unsigned long long*)&oc[2], (unsigned long long)n_gen);
+                atomicAdd((unsigned long long*)&oc[3], (unsigned long long)n_rank);
+                atomicAdd((unsigned long long*)&oc[4], (unsigned long long)n_acc);
+            }
+            n_reg = n_area = n_gen = n_rank = n_acc = 0;
+            n_pass = 1;  // the parts together make the first pass
+            phi_end = phi0;
             __threadfence();  // the buckets are visible before the part counts as done
             int last = 0;
             if (lane == 0) last = atomicAdd(&hs->done, 1) == hs->parts - 1;
@@ -947,14 +969,27 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 if (!wave_all(filled)) status = run(b0, b1, S, 2.0 * phi0, phi0 / S, false);
             }
         } else {
-            set = order ? (int64_t)order[item - n_parts] : item - n_parts;  // largest sets first
+            set = order ? (int64_t)order[item - np] : item - np;  // largest sets first
             const int64_t b0 = rp[set], b1 = rp[set + 1];
-            if (MODE == kModeMinhash && split > 0 && b1 - b0 > split) continue;  // served by its parts
+            if (MODE == kModeMinhash && split > 0 && (planned ? planned[set] != 0 : b1 - b0 > split))
+                continue;  // served by its parts
             const RowInfo ri = scan_row(wts, b0, b1, lane);
             status = ri.status;
+            if (status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
             if (status == kSetOk) {
                 clear_buckets();
                 status = run(b0, b1, ri.sum, phi0, -1.0, false);
+            }
+        }
+        if (out_cnt && lane == 0) {
+            // counts of this wave's passes; a heavy set's parts added theirs already
+            int64_t* oc = out_cnt + set * kCounterWords;
+            const bool heavy_set = MODE == kModeMinhash && item < np;
+            const uint64_t v[kCounterWords] = {n_reg, n_area, n_gen, n_rank, n_acc, n_pass,
+                                               (uint64_t)__double_as_longlong(phi_end), 0};
+            for (int q = 0; q < kCounterWords; ++q) {
+                if (heavy_set && q < 5) atomicAdd((unsigned long long*)&oc[q], (unsigned long long)v[q]);
+                else oc[q] = (int64_t)v[q];
             }
         }
         // outputs
@@ -1012,7 +1047,8 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
                                             const double*, int, int, uint32_t*, uint64_t*, int8_t*,     \
                                             uint64_t*, double*, uint64_t*, double, double,             \
                                             unsigned long long*, const Part*, int64_t, HeavySet*,      \
-                                            uint64_t*, int64_t, const uint32_t*);
+                                            uint64_t*, int64_t, const uint32_t*, int64_t*, const uint8_t*, \
+                                            const unsigned long long*, const uint8_t*);
 DMS_FAST_KERNEL(kModeMinhash, kHashMix)
 DMS_FAST_KERNEL(kModeLsh, kHashMix)
 DMS_FAST_KERNEL(kModeBottomK, kHashMix)
@@ -1023,47 +1059,78 @@ DMS_FAST_KERNEL(kModeLshReg, kHashMix)
 DMS_FAST_KERNEL(kModeLshReg, kHashTab)
 #undef DMS_FAST_KERNEL
 
-// Planning.  plan[0] = heavy sets, plan[1] = parts (counting pass); plan[2],
-// plan[3] are the cursors of the filling pass.
-__global__ void __launch_bounds__(256)
-plan_count_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split,
-                  unsigned long long* plan)
+// Device-side planning of the heavy sets.  plan[0] counts the heavy sets that
+// got parts, plan[1] their parts; both start at 0 (plan_reset_kernel).  A set
+// above the split threshold reserves its parts with a compare-and-swap on
+// plan[1] so that the reserved ranges have no holes; a set whose parts would
+// pass the capacity gets none and is sketched whole by one wave.  planned[s]
+// tells the main kernel which sets its parts serve.
+__global__ void plan_reset_kernel(unsigned long long* plan)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_sets) return;
-    const int64_t nnz = rp[s + 1] - rp[s];
-    if (nnz > split) {
-        atomicAdd(&plan[0], 1ull);
-        atomicAdd(&plan[1], (unsigned long long)((nnz + split - 1) / split));
-    }
+    if (threadIdx.x < 8) plan[threadIdx.x] = 0ull;
 }
 
 __global__ void __launch_bounds__(256)
-plan_fill_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split,
-                 unsigned long long* plan, Part* parts, HeavySet* heavy)
+plan_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split, int64_t part_cap,
+            unsigned long long* plan, Part* parts, HeavySet* heavy, uint8_t* planned, int64_t* out_cnt)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_sets) return;
     const int64_t nnz = rp[s + 1] - rp[s];
-    if (nnz <= split) return;
-    const int32_t P = (int32_t)((nnz + split - 1) / split);
-    const int32_t h = (int32_t)atomicAdd(&plan[2], 1ull);
-    const int64_t base = (int64_t)atomicAdd(&plan[3], (unsigned long long)P);
-    HeavySet hs;
-    hs.sum = 0.0;
-    hs.set = s;
-    hs.base = base;
-    hs.parts = P;
-    hs.done = 0;
-    hs.range = 0;
-    hs.status = kSetOk;
-    heavy[h] = hs;
-    for (int32_t p = 0; p < P; ++p) {
-        Part pt;
-        pt.set = s;
-        pt.heavy = h;
-        pt.index = p;
-        parts[base + p] = pt;
+    uint8_t mine = 0;
+    if (nnz > split) {
+        const int64_t P = (nnz + split - 1) / split;
+        unsigned long long old = __hip_atomic_load(&plan[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t base = -1;
+        while ((int64_t)old + P <= part_cap && P < 0x7FFFFFFF) {
+            const unsigned long long seen = atomicCAS(&plan[1], old, old + (unsigned long long)P);
+            if (seen == old) {
+                base = (int64_t)old;
+                break;
+            }
+            old = seen;
+        }
+        if (base >= 0) {
+            if (out_cnt) {  // the parts of the set add their counts
+                for (int q = 0; q < kCounterWords; ++q) out_cnt[s * kCounterWords + q] = 0;
+            }
+            const int32_t h = (int32_t)atomicAdd(&plan[0], 1ull);
+            HeavySet hs;
+            hs.sum = 0.0;
+            hs.set = s;
+            hs.base = base;
+            hs.parts = (int32_t)P;
+            hs.done = 0;
+            hs.range = 0;
+            hs.status = kSetOk;
+            heavy[h] = hs;
+            for (int32_t p = 0; p < (int32_t)P; ++p) {
+                Part pt;
+                pt.set = s;
+                pt.heavy = h;
+                pt.index = p;
+                parts[base + p] = pt;
+            }
+            mine = 1;
+        }
+    }
+    planned[s] = mine;
+}
+
+// One wave per heavy set of a device plan (n_heavy read from plan[0]; the grid
+// covers the capacity): validity and ||x||_1 of the whole row.
+__global__ void __launch_bounds__(256)
+plan_scan_kernel(const unsigned long long* plan, const int64_t* __restrict__ rp, const double* __restrict__ w,
+                 HeavySet* heavy)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t h = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (h >= (int64_t)plan[0]) return;
+    const int64_t s = heavy[h].set;
+    const RowInfo ri = scan_row(w, rp[s], rp[s + 1], lane);
+    if (lane == 0) {
+        heavy[h].sum = ri.sum;
+        heavy[h].status = ri.status;
     }
 }
 
@@ -1092,31 +1159,20 @@ hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w
     return hipGetLastError();
 }
 
-__global__ void reset_plan_kernel(unsigned long long* plan)
-{
-    if (threadIdx.x < 8) plan[threadIdx.x] = 0ull;
-}
-
 size_t plan_part_bytes() { return sizeof(Part); }
 size_t plan_heavy_bytes() { return sizeof(HeavySet); }
 
-hipError_t launch_plan_count(int64_t n_sets, const int64_t* rp, int64_t split,
-                             unsigned long long* plan, hipStream_t st)
+hipError_t launch_plan(int64_t n_sets, const int64_t* rp, const double* w, int64_t split, int64_t part_cap,
+                       unsigned long long* plan, void* parts, void* heavy, uint8_t* planned, int64_t* out_cnt,
+                       hipStream_t st)
 {
-    hipLaunchKernelGGL(reset_plan_kernel, dim3(1), dim3(64), 0, st, plan);
-    hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st,
-                       n_sets, rp, split, plan);
-    return hipGetLastError();
-}
-
-hipError_t launch_plan_fill(int64_t n_sets, const int64_t* rp, const double* w, int64_t split,
-                            int64_t n_heavy, unsigned long long* plan, void* parts, void* heavy,
-                            hipStream_t st)
-{
-    hipLaunchKernelGGL(plan_fill_kernel, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st,
-                       n_sets, rp, split, plan, (Part*)parts, (HeavySet*)heavy);
-    hipLaunchKernelGGL(heavy_scan_kernel, dim3((unsigned)((n_heavy + 3) / 4)), dim3(256), 0, st,
-                       n_heavy, rp, w, (HeavySet*)heavy);
+    hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, st, plan);
+    hipLaunchKernelGGL(plan_kernel, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st, n_sets, rp, split,
+                       part_cap, plan, (Part*)parts, (HeavySet*)heavy, planned, out_cnt);
+    const int64_t heavy_cap = part_cap / 2;  // every heavy set has two parts or more
+    if (heavy_cap > 0)
+        hipLaunchKernelGGL(plan_scan_kernel, dim3((unsigned)((heavy_cap + 3) / 4)), dim3(256), 0, st, plan, rp, w,
+                           (HeavySet*)heavy);
     return hipGetLastError();
 }
 
@@ -1179,7 +1235,8 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     double* out_rank, double phi0, double phi_max,
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
-                                    const uint32_t* order, int hash, hipStream_t st)
+                                    const uint32_t* order, int hash, const LaunchExtras& x,
+                                    const unsigned long long* plan_dev, const uint8_t* planned, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeMinhash, k, 1);
@@ -1191,7 +1248,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
-                       (HeavySet*)heavy, partial, split, order);
+                       (HeavySet*)heavy, partial, split, order, x.counters, x.repeated, plan_dev, planned);
     return hipGetLastError();
 }
 
@@ -1199,18 +1256,19 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
                               const int32_t* idx, const double* w, int k, uint32_t* out_u32,
                               uint64_t* out_bits, int8_t* out_status, uint64_t* out_s,
                               double* out_rank, double phi0, double phi_max,
-                              unsigned long long* counter, int blocks, int hash, hipStream_t st)
+                              unsigned long long* counter, int blocks, int hash, const LaunchExtras& x,
+                              hipStream_t st)
 {
     return launch_sketch_fast_split(sp, n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s,
                                     out_rank, phi0, phi_max, counter, blocks, nullptr, 0, nullptr,
-                                    nullptr, 0, nullptr, hash, st);
+                                    nullptr, 0, nullptr, hash, x, nullptr, nullptr, st);
 }
 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
                            const int32_t* idx, const double* w, int L, int K, uint64_t* out_keys,
                            int8_t* out_status, double phi0, double phi_max,
                            unsigned long long* counter, int blocks, const uint32_t* order, int hash,
-                           hipStream_t st)
+                           const LaunchExtras& x, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int mode = lsh_fast_mode(L, K);
@@ -1226,7 +1284,8 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
                        (const Part*)nullptr, (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr,
-                       (int64_t)0, order);
+                       (int64_t)0, order, x.counters, x.repeated, (const unsigned long long*)nullptr,
+                       (const uint8_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -1234,7 +1293,7 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
                                const int32_t* idx, const double* w, int k, uint64_t* out_s,
                                double* out_rank, int8_t* out_status, double phi0, double phi_max,
                                unsigned long long* counter, int blocks, const uint32_t* order, int hash,
-                               hipStream_t st)
+                               const LaunchExtras& x, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
     const int waves = fast_waves(kModeBottomK, k, 1);
@@ -1246,7 +1305,8 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        out_s, out_rank, (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)nullptr,
-                       (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0, order);
+                       (int64_t)0, (HeavySet*)nullptr, (uint64_t*)nullptr, (int64_t)0, order, x.counters,
+                       x.repeated, (const unsigned long long*)nullptr, (const uint8_t*)nullptr);
     return hipGetLastError();
 }
 

@@ -17,8 +17,11 @@ SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
 OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH, OPT_ORDER = (
     0, 1, 2, 3, 4, 5, 6, 7)
+OPT_TIMING = 8
 HASH_MIX, HASH_TAB = 0, 1
 FMT_U32, FMT_1BIT = 0, 1
+FLAG_VALIDATE, FLAG_COUNTERS = 1, 2
+COUNTER_WORDS = 8  # regions, areas, generated, rank passed, accepted, passes, last phi (bits), 0
 
 EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms_get_option",
            "dms_sketch_csr", "dms_lsh_keys", "dms_jaccard_est", "dms_hamming_topk", "dms_sync",
@@ -27,7 +30,7 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_server_poll", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
            "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune",
-           "dms_spec_tabulation"]
+           "dms_spec_tabulation", "dms_kernel_time"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -61,11 +64,11 @@ def lib():
         "dms_set_stream": ([vp, vp], i32),
         "dms_set_option": ([vp, i32, f64], i32),
         "dms_get_option": ([vp, i32, P(f64)], i32),
-        "dms_sketch_csr": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
-        "dms_lsh_keys": ([vp, i64, vp, vp, vp, i32, i32, vp, vp], i32),
+        "dms_sketch_csr": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, u32, vp], i32),
+        "dms_lsh_keys": ([vp, i64, vp, vp, vp, i32, i32, vp, vp, u32, vp], i32),
         "dms_jaccard_est": ([vp, i64, vp, vp, i32, i32, vp], i32),
         "dms_bbit_pack": ([vp, i64, vp, i32, i32, vp], i32),
-        "dms_bottomk": ([vp, i64, vp, vp, vp, i32, vp, vp, vp], i32),
+        "dms_bottomk": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, u32, vp], i32),
         "dms_index_build": ([vp, i64, vp, vp, vp, i32, i32, ctypes.POINTER(vp)], i32),
         "dms_index_sets": ([vp, vp, vp], i32),
         "dms_index_query": ([vp, i64, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp], i32),
@@ -77,6 +80,7 @@ def lib():
         "dms_unary_map": ([vp, i64, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "dms_hamming_topk": ([vp, vp, i64, i32, vp, i64, i32, vp, vp], i32),
         "dms_sync": ([vp], i32),
+        "dms_kernel_time": ([vp, P(f64), P(i64)], i32),
         "dms_last_error": ([vp], ctypes.c_char_p),
         "dms_status_str": ([i32], ctypes.c_char_p),
         "dms_t_of_k": ([i32, P(u32)], i32),
@@ -186,16 +190,19 @@ class Context:
 
     # -- raw C-ABI calls on device tensors -----------------------------------
     def dms_sketch_csr(self, n_sets, row_ptr, idx, w, k, out_u32=None, out_bits=None,
-                       out_status=None, out_s=None, out_rank=None):
+                       out_status=None, out_s=None, out_rank=None, flags=0, out_counters=None):
         self._stream()
         self._check(lib().dms_sketch_csr(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
                                          _ptr(out_u32), _ptr(out_bits), _ptr(out_status),
-                                         _ptr(out_s), _ptr(out_rank)), "dms_sketch_csr")
+                                         _ptr(out_s), _ptr(out_rank), flags, _ptr(out_counters)),
+                    "dms_sketch_csr")
 
-    def dms_lsh_keys(self, n_sets, row_ptr, idx, w, L, K, out_keys, out_status=None):
+    def dms_lsh_keys(self, n_sets, row_ptr, idx, w, L, K, out_keys, out_status=None, flags=0,
+                     out_counters=None):
         self._stream()
         self._check(lib().dms_lsh_keys(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), L, K,
-                                       _ptr(out_keys), _ptr(out_status)), "dms_lsh_keys")
+                                       _ptr(out_keys), _ptr(out_status), flags, _ptr(out_counters)),
+                    "dms_lsh_keys")
 
     def dms_jaccard_est(self, n_pairs, a, b, k, fmt, out):
         self._stream()
@@ -211,10 +218,12 @@ class Context:
                                        ctypes.byref(phi0), ctypes.byref(split)), "dms_autotune")
         return phi0.value, split.value
 
-    def dms_bottomk(self, n_sets, row_ptr, idx, w, k, out_s, out_rank=None, out_status=None):
+    def dms_bottomk(self, n_sets, row_ptr, idx, w, k, out_s, out_rank=None, out_status=None, flags=0,
+                    out_counters=None):
         self._stream()
         self._check(lib().dms_bottomk(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), k, _ptr(out_s),
-                                      _ptr(out_rank), _ptr(out_status)), "dms_bottomk")
+                                      _ptr(out_rank), _ptr(out_status), flags, _ptr(out_counters)),
+                    "dms_bottomk")
 
     def dms_jaccard_est_bottomk(self, n_pairs, rank_a, s_a, rank_b, s_b, k, out):
         self._stream()
@@ -253,9 +262,24 @@ class Context:
     def sync(self):
         self._check(lib().dms_sync(self._h), "dms_sync")
 
+    def kernel_time(self):
+        """(summed ms, launches) of the main kernels timed since the last call
+        (needs OPT_TIMING = 1); waits for them."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+        self._check(lib().dms_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)), "dms_kernel_time")
+        return ms.value, n.value
+
     # -- conveniences that allocate outputs ----------------------------------
-    def sketch(self, row_ptr, idx, w, k, bits=True, full=False):
-        """Sketch a CSR batch already on the GPU; returns a dict of device tensors."""
+    def _flags(self, n, dev, counters, validate):
+        """(flags, counter tensor or None) for the sketching calls."""
+        flags = (FLAG_COUNTERS if counters else 0) | (FLAG_VALIDATE if validate else 0)
+        cnt = (self._torch.empty((n, COUNTER_WORDS), dtype=self._torch.int64, device=dev)
+               if counters else None)
+        return flags, cnt
+
+    def sketch(self, row_ptr, idx, w, k, bits=True, full=False, counters=False, validate=False):
+        """Sketch a CSR batch already on the GPU; returns a dict of device tensors
+        (with ``counters`` also the int64 [n, 8] enumeration counts)."""
         torch = self._torch
         n = row_ptr.numel() - 1
         dev = row_ptr.device
@@ -266,17 +290,23 @@ class Context:
         if full:
             out["s"] = torch.empty((n, k), dtype=torch.int64, device=dev)
             out["rank"] = torch.empty((n, k), dtype=torch.float64, device=dev)
+        flags, cnt = self._flags(n, dev, counters, validate)
         self.dms_sketch_csr(n, row_ptr, idx, w, k, out["u32"], out.get("bits"), out["status"],
-                            out.get("s"), out.get("rank"))
+                            out.get("s"), out.get("rank"), flags, cnt)
+        if counters:
+            out["counters"] = cnt
         return out
 
-    def lsh(self, row_ptr, idx, w, L, K):
+    def lsh(self, row_ptr, idx, w, L, K, counters=False, validate=False):
         torch = self._torch
         n = row_ptr.numel() - 1
         dev = row_ptr.device
         out = dict(keys=torch.empty((n, L), dtype=torch.int64, device=dev),
                    status=torch.empty(n, dtype=torch.int8, device=dev))
-        self.dms_lsh_keys(n, row_ptr, idx, w, L, K, out["keys"], out["status"])
+        flags, cnt = self._flags(n, dev, counters, validate)
+        self.dms_lsh_keys(n, row_ptr, idx, w, L, K, out["keys"], out["status"], flags, cnt)
+        if counters:
+            out["counters"] = cnt
         return out
 
     def jaccard(self, a, b, k, fmt):
@@ -285,7 +315,7 @@ class Context:
         self.dms_jaccard_est(a.shape[0], a, b, k, fmt, out)
         return out
 
-    def bottomk(self, row_ptr, idx, w, k):
+    def bottomk(self, row_ptr, idx, w, k, counters=False, validate=False):
         """Bottom-k sketches: dict s (int64 [n, k], uint64 bits), rank (float64
         [n, k]) and status (int8 [n])."""
         torch = self._torch
@@ -294,7 +324,10 @@ class Context:
         out = dict(s=torch.empty((n, k), dtype=torch.int64, device=dev),
                    rank=torch.empty((n, k), dtype=torch.float64, device=dev),
                    status=torch.empty(n, dtype=torch.int8, device=dev))
-        self.dms_bottomk(n, row_ptr, idx, w, k, out["s"], out["rank"], out["status"])
+        flags, cnt = self._flags(n, dev, counters, validate)
+        self.dms_bottomk(n, row_ptr, idx, w, k, out["s"], out["rank"], out["status"], flags, cnt)
+        if counters:
+            out["counters"] = cnt
         return out
 
     def jaccard_bottomk(self, rank_a, s_a, rank_b, s_b):

@@ -1,8 +1,10 @@
 """Sketch, LSH and bottom-k calls captured into a HIP graph (torch.cuda.graph)
-and replayed: with DMS_OPT_SPLIT_NNZ = 0 a call enqueues only kernels (the size
-order's sort, the cursor reset and the persistent launch), so after one eager
-call has sized the context's scratch it can be captured.  Every replay, with
-eager work and synchronizations in between, must equal the eager result."""
+and replayed: a call enqueues only kernels (the device plan of heavy sets, the
+size order's sort, the cursor reset and the persistent launch), so after one
+eager call has sized the context's scratch it can be captured -- with the
+default options, with splitting off, and with a split threshold that cuts many
+sets into parts.  Every replay, with eager work and synchronizations in
+between, must equal the eager result."""
 import numpy as np
 import pytest
 
@@ -26,13 +28,15 @@ def batch(torch):
     return len(rp) - 1, to_device(rp, idx, w)
 
 
-@pytest.mark.parametrize("order,L,K", [(1, 16, 4), (0, 16, 4), (1, 64, 8)])
-def test_captured_calls_replay_like_eager(torch, batch, order, L, K):
-    # (64,8) LSH keeps its tables in registers, (16,4) in LDS
+@pytest.mark.parametrize("split,order,L,K", [(None, 1, 64, 8), (0, 1, 16, 4), (0, 0, 16, 4), (0, 1, 64, 8),
+                                             (512, 1, 16, 4)])
+def test_captured_calls_replay_like_eager(torch, batch, split, order, L, K):
+    # (64,8) LSH keeps its tables in registers, (16,4) in LDS; split None keeps the default
     from paper_2005_11547_amd import Context, dms
     n, d = batch
     c = Context(SEED)
-    c.set_option(dms.OPT_SPLIT_NNZ, 0)
+    if split is not None:
+        c.set_option(dms.OPT_SPLIT_NNZ, split)
     c.set_option(dms.OPT_ORDER, order)
     k, kb = 256, 64
     words = (k + 63) // 64
@@ -51,7 +55,7 @@ def test_captured_calls_replay_like_eager(torch, batch, order, L, K):
         c.dms_lsh_keys(n, *d, L, K, keys, lst)
         c.dms_bottomk(n, *d, kb, bs, br, bst)
 
-    print(f"[graph] eager order={order} L={L} K={K}", flush=True)
+    print(f"[graph] eager split={split} order={order} L={L} K={K}", flush=True)
     calls()  # sizes the tables and scratch outside the capture
     torch.cuda.synchronize()
     ref = [t.cpu().clone() for t in outs]
