@@ -64,8 +64,9 @@ typedef int32_t dms_status;
                                (default 4096; 0 disables, and then every set must have fewer
                                than 2^32 nonzeros: queues name elements by 32-bit offsets within
                                the set or part).  The parts are planned on the device into
-                               scratch of fixed capacity (partial buckets of at most 256 MiB);
-                               a heavy set that no longer fits is sketched whole by one wave. */
+                               scratch of fixed capacity (twice the batch's sets, at least 1024
+                               parts, at most 256 MiB of partial buckets); a heavy set that no
+                               longer fits is sketched whole by one wave (same outputs). */
 #define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
 #define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
                                Unlike the other options it changes the outputs: sketches made

@@ -173,12 +173,15 @@ dms_status prepare_extras(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     return DMS_OK;
 }
 
-// Parts a device plan may hold for k buckets: their partial buckets take at
-// most 256 MiB (sets beyond the capacity are sketched whole).
-int64_t plan_capacity(int32_t k)
+// Parts a device plan may hold for a batch of n sets with k buckets: twice the
+// sets (at least 1024), within 256 MiB of partial buckets.  Heavy sets beyond
+// the capacity are sketched whole; the outputs are the same.
+int64_t plan_capacity(int64_t n_sets, int32_t k)
 {
-    int64_t cap = ((int64_t)256 << 20) / (16 * (int64_t)k);
-    return cap < 64 ? 64 : (cap > ((int64_t)1 << 20) ? ((int64_t)1 << 20) : cap);
+    const int64_t by_bytes = ((int64_t)256 << 20) / (16 * (int64_t)k);
+    int64_t cap = 2 * n_sets < 1024 ? 1024 : 2 * n_sets;
+    if (cap > by_bytes) cap = by_bytes;
+    return cap < 64 ? 64 : cap;
 }
 
 // Brackets the main kernel of a sketching call with events (DMS_OPT_TIMING).
@@ -396,7 +399,7 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         if (split > 0) {
             // the heavy sets are planned on the device into scratch of a fixed
             // capacity, so the call only enqueues kernels
-            part_cap = plan_capacity(k);
+            part_cap = plan_capacity(n_sets, k);
             dms_status g2 = grow(c, &c->parts, &c->parts_bytes, (size_t)part_cap * dms::plan_part_bytes());
             if (g2 == DMS_OK)
                 g2 = grow(c, &c->heavy, &c->heavy_bytes, (size_t)(part_cap / 2) * dms::plan_heavy_bytes());

@@ -38,19 +38,32 @@ namespace {
 // hold two rounds so that their (cheaper) consumers always run 64 lanes wide.
 // With these sizes three waves of k = 256 fit 40,960 bytes, so twelve waves
 // share a CU.
-constexpr uint32_t kCapR = 80;   // region queue (regions with areas left)
-constexpr uint32_t kCapD = 128;  // dart queue (areas with darts left)
-constexpr uint32_t kCapP = 128;  // pass queue (darts with rank <= tau)
+#ifndef DMS_CAP_R
+#define DMS_CAP_R 80
+#endif
+#ifndef DMS_CAP_D
+#define DMS_CAP_D 128
+#endif
+#ifndef DMS_CAP_P
+#define DMS_CAP_P 128
+#endif
+constexpr uint32_t kCapR = DMS_CAP_R;  // region queue (regions with areas left)
+constexpr uint32_t kCapD = DMS_CAP_D;  // dart queue (areas with darts left)
+constexpr uint32_t kCapP = DMS_CAP_P;  // pass queue (darts with rank <= tau)
+static_assert(kCapR >= 64 && kCapD >= 64 && kCapP >= 64, "a round moves up to 64 entries");
 constexpr uint32_t kTrigR = kCapR - 64, kTrigD = kCapD - 64, kTrigP = kCapP - 64;
 
-// Ring slots of positions below 3 * cap (a head below cap plus two counts).
-__device__ __forceinline__ uint32_t ring_r(uint32_t p)
+// Ring slot of a position below 3 * cap (a head below cap plus two counts).
+template <uint32_t CAP>
+__device__ __forceinline__ uint32_t ring(uint32_t p)
 {
-    p = min(p, p - 2u * kCapR);  // unsigned: wraps to a large value when p < 2 * kCapR
-    return min(p, p - kCapR);
+    if ((CAP & (CAP - 1)) == 0) return p & (CAP - 1);
+    p = min(p, p - 2u * CAP);  // unsigned: wraps to a large value when p < 2 * CAP
+    return min(p, p - CAP);
 }
-__device__ __forceinline__ uint32_t ring_d(uint32_t p) { return p & (kCapD - 1); }
-__device__ __forceinline__ uint32_t ring_p(uint32_t p) { return p & (kCapP - 1); }
+__device__ __forceinline__ uint32_t ring_r(uint32_t p) { return ring<kCapR>(p); }
+__device__ __forceinline__ uint32_t ring_d(uint32_t p) { return ring<kCapD>(p); }
+__device__ __forceinline__ uint32_t ring_p(uint32_t p) { return ring<kCapP>(p); }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -279,7 +292,7 @@ __device__ __forceinline__ T& at(unsigned char* base, uint32_t off, uint32_t i)
 // buckets keep their minimum), (L,K) LSH (k = L tables keep their K smallest
 // darts) or the bottom-k sketch (a buffer of darts, sorted and cut to the k
 // smallest).  Each wave repeatedly takes the next set index from *next_set.
-template <int MODE, int HK>
+template <int MODE, int HK, bool DBG>
 __global__ void __launch_bounds__(256)
 fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __restrict__ rp,
             const int32_t* __restrict__ idx, const double* __restrict__ wts, int k, int K,
@@ -475,13 +488,22 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             for (;;) {
                 if (phi > phi_max) { status = kSetRange; break; }
                 const double tau = phi / S;
-                n_pass += 1;
-                phi_end = phi;
+                if (DBG) {
+                    n_pass += 1;
+                    phi_end = phi;
+                }
                 // rho runs over 0 .. B1-1: the rows whose lower corner is <= tau
                 int B1 = 0;
                 while (B1 < kMaxIndex && r_corner(sR, B1) <= tau) ++B1;
                 bool range = B1 >= kMaxIndex;
                 const float inv_b1 = 1.0f / (float)B1;
+                // With tau < 1 every region lies in rank row 0 and has one column;
+                // region nu has floor(tau 2^nu) + 1 rows (at most 2^nu), so the
+                // regions below nu_split (tau 2^nu < 1, i.e. nu < -ilogb(tau)) are a
+                // single area each: the "low band", walked by lockstep rounds over
+                // nu with one element per lane and no expansion.
+                // (Measured: the bottom-k sink runs faster without it.)
+                const int nu_split = !BK && B1 == 1 ? max(0, -ilogb(tau)) : 0;
 
                 const int64_t b1 = hi;
                 int64_t chunk = lo;        // first element of the current chunk
@@ -490,6 +512,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 double ex = 0.0;           // this lane's element weight
                 uint32_t eid = 0;          // this lane's element id
                 uint32_t nreg = 0, nreg_excl = 0;
+                uint32_t n_low = 0;     // this lane's element: low-band regions
+                uint32_t low_nu = 0;    // next low-band nu of the chunk (wave-uniform)
+                bool low_left = false;  // some lane still has low-band regions
                 bool have_chunk = false;
                 uint32_t rq_head = 0, rq_count = 0, dq_head = 0, dq_count = 0;
                 uint32_t pq_head = 0, pq_count = 0;
@@ -501,6 +526,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         ex = 0.0;
                         eid = 0;
                         nreg = 0;
+                        n_low = 0;
                         if (e < b1) {
                             ex = wts[e];
                             eid = (uint32_t)idx[e];
@@ -512,13 +538,25 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             while (A < kMaxIndex && w_corner(sW, u, A) <= ex) ++A;
                             while (A > 1 && w_corner(sW, u, A - 1) > ex) --A;
                             if (A >= kMaxIndex) range = true;
-                            nreg = (uint32_t)A * (uint32_t)B1;
+                            n_low = (uint32_t)min(A, nu_split);
+                            nreg = (uint32_t)A;
                         }
+                        if (nu_split > 0) {
+                            // lockstep rounds pay for 64 lanes each: they serve the
+                            // chunk only while they stay at least 3/4 full; otherwise
+                            // its regions are all expanded
+                            const uint32_t low_sum = uni(lane63(scan_add(n_low)));
+                            const uint32_t low_max = uni(lane63((uint32_t)scan_max((int32_t)n_low)));
+                            if (4 * low_sum < 3 * 64 * low_max) n_low = 0;
+                        }
+                        nreg = (nreg - n_low) * (uint32_t)B1;
                         const uint32_t incl = scan_add(nreg);
                         nreg_excl = incl - nreg;
                         chunk_total = uni(lane63(incl));
                         reg_done = 0;
-                        have_chunk = chunk_total > 0;
+                        low_nu = 0;
+                        low_left = wave_any(n_low > 0);
+                        have_chunk = chunk_total > 0 || low_left;
                         if (!have_chunk) chunk += kWave;
                     }
                 };
@@ -548,8 +586,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     const bool more = has && X > 1;
                     const uint64_t bp = __ballot(pass);
                     const uint64_t bm = __ballot(more);
-                    n_gen += (uint64_t)__popcll(__ballot(has));
-                    n_rank += (uint64_t)__popcll(bp);
+                    if (DBG) {
+                        n_gen += (uint64_t)__popcll(__ballot(has));
+                        n_rank += (uint64_t)__popcll(bp);
+                    }
                     if (pass) {
                         const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
                         at<uint64_t>(wb, kOffPqA, pos) = a;
@@ -587,7 +627,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const double V = unit53(H(a ^ KV ^ j));
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
-                        n_acc += (uint64_t)__popcll(__ballot(acc));
+                        if (DBG) n_acc += (uint64_t)__popcll(__ballot(acc));
                         uint64_t s = 0;
                         if (acc) s = H(a ^ KS ^ j);
                         if (RT) {
@@ -663,8 +703,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const bool more = act && j + 1 < X;
                         const uint64_t bp = __ballot(pass);
                         const uint64_t bm = __ballot(more);
-                        n_gen += m;
-                        n_rank += (uint64_t)__popcll(bp);
+                        if (DBG) {
+                            n_gen += m;
+                            n_rank += (uint64_t)__popcll(bp);
+                        }
                         wave_sync();  // every entry of the round is read before any write
                         if (pass) {
                             const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
@@ -735,7 +777,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
                             X = poisson_head(C, a);
                         }
-                        n_area += m;
+                        if (DBG) n_area += m;
                         emit_area(act, a, ei, rv, wv, meta, X, false);
                         // advance the region queue by m areas
                         const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
@@ -749,12 +791,37 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             rq_head = uni(ring_r(rq_head + last_src));
                             rq_count = uni(rq_count - last_src);
                         }
+                    } else if (have_chunk && low_left) {
+                        // ---------------- low-band round ----------------
+                        // region (low_nu, 0) of every lane's element: one area (w = r = 0)
+                        const bool act = low_nu < n_low;
+                        uint64_t a = 0;
+                        uint32_t X = 0;
+                        if (DBG) {
+                            const uint64_t nb = (uint64_t)__popcll(__ballot(act));
+                            n_reg += nb;
+                            n_area += nb;
+                        }
+                        if (act) {
+                            const uint64_t g = H(KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
+                            a = H(g ^ KA);
+                            X = poisson_head(C, a);
+                        }
+                        emit_area(act, a, (uint32_t)(chunk - lo) + (uint32_t)lane, 0u, 0u, low_nu, X, true);
+                        low_nu = uni(low_nu + 1);
+                        low_left = wave_any(low_nu < n_low);
+                        if (!low_left && chunk_total == 0) {
+                            chunk += kWave;
+                            load_chunk();
+                        }
                     } else if (have_chunk) {
                         // ---------------- region round ----------------
                         const uint32_t left = chunk_total - reg_done;
                         const uint32_t m = left < 64 ? left : 64;
-                        n_reg += m;
-                        n_area += m;  // every region's first area (w = r = 0)
+                        if (DBG) {
+                            n_reg += m;
+                            n_area += m;  // every region's first area (w = r = 0)
+                        }
                         at<int32_t>(wb, kOffMark, lane) = 0;
                         wave_sync();
                         if (nreg > 0 && nreg_excl + nreg > reg_done && nreg_excl < reg_done + 64)
@@ -770,8 +837,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         if (B1 == 1) {
                             // tau < R[1] = 1: every region lies in rank row 0 and has one
                             // column; its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact)
+                            const uint32_t nu_base = (uint32_t)__shfl(n_low, src, kWave);
                             if (act) {
-                                const uint32_t nu = reg_done + (uint32_t)lane - s_excl;
+                                // the element's regions above its low band
+                                const uint32_t nu = nu_base + reg_done + (uint32_t)lane - s_excl;
                                 meta = nu;
                                 g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
                                 const double rcn = fmin(floor(ldexp(tau, (int)nu)) + 1.0, ldexp(1.0, (int)nu));
@@ -917,7 +986,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             const int64_t hi = lo + split < b1 ? lo + split : b1;
             const double S = hs->sum;
             status = (int8_t)hs->status;
-            if (status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
+            if (DBG && status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
             uint64_t* mine = partial + (size_t)(hs->base + pt.index) * 2 * k;
             if (status == kSetOk) {
                 clear_buckets();
@@ -928,7 +997,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     mine[k + j] = bin_s[j];
                 }
             }
-            if (out_cnt && lane == 0) {
+            if (DBG && out_cnt && lane == 0) {
                 // the part's share of the set's counts (the plan zeroed them)
                 int64_t* oc = out_cnt + set * kCounterWords;
                 atomicAdd((unsigned long long*)&oc[0], (unsigned long long)n_reg);
@@ -975,13 +1044,13 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 continue;  // served by its parts
             const RowInfo ri = scan_row(wts, b0, b1, lane);
             status = ri.status;
-            if (status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
+            if (DBG && status == kSetOk && repeated && repeated[set]) status = kSetInvalid;
             if (status == kSetOk) {
                 clear_buckets();
                 status = run(b0, b1, ri.sum, phi0, -1.0, false);
             }
         }
-        if (out_cnt && lane == 0) {
+        if (DBG && out_cnt && lane == 0) {
             // counts of this wave's passes; a heavy set's parts added theirs already
             int64_t* oc = out_cnt + set * kCounterWords;
             const bool heavy_set = MODE == kModeMinhash && item < np;
@@ -1042,21 +1111,23 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 // Explicit instantiations: the host launches all three.
-#define DMS_FAST_KERNEL(M, HK)                                                                    \
-    template __global__ void fast_kernel<M, HK>(const SpecTables*, int64_t, const int64_t*, const int32_t*, \
+#define DMS_FAST_KERNEL(M, HK, D)                                                                 \
+    template __global__ void fast_kernel<M, HK, D>(const SpecTables*, int64_t, const int64_t*, const int32_t*, \
                                             const double*, int, int, uint32_t*, uint64_t*, int8_t*,     \
                                             uint64_t*, double*, uint64_t*, double, double,             \
                                             unsigned long long*, const Part*, int64_t, HeavySet*,      \
                                             uint64_t*, int64_t, const uint32_t*, int64_t*, const uint8_t*, \
                                             const unsigned long long*, const uint8_t*);
-DMS_FAST_KERNEL(kModeMinhash, kHashMix)
-DMS_FAST_KERNEL(kModeLsh, kHashMix)
-DMS_FAST_KERNEL(kModeBottomK, kHashMix)
-DMS_FAST_KERNEL(kModeMinhash, kHashTab)
-DMS_FAST_KERNEL(kModeLsh, kHashTab)
-DMS_FAST_KERNEL(kModeBottomK, kHashTab)
-DMS_FAST_KERNEL(kModeLshReg, kHashMix)
-DMS_FAST_KERNEL(kModeLshReg, kHashTab)
+#define DMS_FAST_KERNELS(M, HK) DMS_FAST_KERNEL(M, HK, false) DMS_FAST_KERNEL(M, HK, true)
+DMS_FAST_KERNELS(kModeMinhash, kHashMix)
+DMS_FAST_KERNELS(kModeLsh, kHashMix)
+DMS_FAST_KERNELS(kModeBottomK, kHashMix)
+DMS_FAST_KERNELS(kModeMinhash, kHashTab)
+DMS_FAST_KERNELS(kModeLsh, kHashTab)
+DMS_FAST_KERNELS(kModeBottomK, kHashTab)
+DMS_FAST_KERNELS(kModeLshReg, kHashMix)
+DMS_FAST_KERNELS(kModeLshReg, kHashTab)
+#undef DMS_FAST_KERNELS
 #undef DMS_FAST_KERNEL
 
 // Device-side planning of the heavy sets.  plan[0] counts the heavy sets that
@@ -1215,18 +1286,34 @@ size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, 1, wa
 
 int lsh_fast_mode(int L, int K) { return L <= kWave && K == 8 ? kModeLshReg : kModeLsh; }
 
+using FastKernel = void (*)(const SpecTables*, int64_t, const int64_t*, const int32_t*, const double*, int, int,
+                            uint32_t*, uint64_t*, int8_t*, uint64_t*, double*, uint64_t*, double, double,
+                            unsigned long long*, const Part*, int64_t, HeavySet*, uint64_t*, int64_t,
+                            const uint32_t*, int64_t*, const uint8_t*, const unsigned long long*, const uint8_t*);
+
+template <int MODE>
+FastKernel pick_fast(int hash, bool dbg)
+{
+    if (hash == kHashTab) return dbg ? fast_kernel<MODE, kHashTab, true> : fast_kernel<MODE, kHashTab, false>;
+    return dbg ? fast_kernel<MODE, kHashMix, true> : fast_kernel<MODE, kHashMix, false>;
+}
+
+// The fast kernel for a sink, a hash and whether counts or row validation are
+// asked for (those run in a variant of their own, so that the plain kernel
+// keeps its registers).
+FastKernel fast_kernel_for(int mode, int hash, bool dbg)
+{
+    switch (mode) {
+    case kModeLshReg: return pick_fast<kModeLshReg>(hash, dbg);
+    case kModeLsh: return pick_fast<kModeLsh>(hash, dbg);
+    case kModeBottomK: return pick_fast<kModeBottomK>(hash, dbg);
+    default: return pick_fast<kModeMinhash>(hash, dbg);
+    }
+}
+
 const void* fast_kernel_address(int mode, int hash)
 {
-    if (mode == kModeLshReg)
-        return hash == kHashTab ? reinterpret_cast<const void*>(&fast_kernel<kModeLshReg, kHashTab>)
-                                : reinterpret_cast<const void*>(&fast_kernel<kModeLshReg, kHashMix>);
-    if (hash == kHashTab)
-        return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh, kHashTab>)
-             : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK, kHashTab>)
-                                    : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash, kHashTab>);
-    return mode == kModeLsh ? reinterpret_cast<const void*>(&fast_kernel<kModeLsh, kHashMix>)
-         : mode == kModeBottomK ? reinterpret_cast<const void*>(&fast_kernel<kModeBottomK, kHashMix>)
-                                : reinterpret_cast<const void*>(&fast_kernel<kModeMinhash, kHashMix>);
+    return reinterpret_cast<const void*>(fast_kernel_for(mode, hash, false));
 }
 
 hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const int64_t* rp,
@@ -1244,7 +1331,7 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_parts + n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    auto kern = hash == kHashTab ? fast_kernel<kModeMinhash, kHashTab> : fast_kernel<kModeMinhash, kHashMix>;
+    const FastKernel kern = fast_kernel_for(kModeMinhash, hash, x.counters || x.repeated);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
@@ -1277,9 +1364,7 @@ hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* 
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    auto kern = mode == kModeLshReg ? (hash == kHashTab ? fast_kernel<kModeLshReg, kHashTab>
-                                                        : fast_kernel<kModeLshReg, kHashMix>)
-              : (hash == kHashTab ? fast_kernel<kModeLsh, kHashTab> : fast_kernel<kModeLsh, kHashMix>);
+    const FastKernel kern = fast_kernel_for(mode, hash, x.counters || x.repeated);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, L, K, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        (uint64_t*)nullptr, (double*)nullptr, out_keys, phi0, phi_max, counter,
@@ -1301,7 +1386,7 @@ hipError_t launch_bottomk_fast(const SpecTables* sp, int64_t n_sets, const int64
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
-    auto kern = hash == kHashTab ? fast_kernel<kModeBottomK, kHashTab> : fast_kernel<kModeBottomK, kHashMix>;
+    const FastKernel kern = fast_kernel_for(kModeBottomK, hash, x.counters || x.repeated);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, 1, (uint32_t*)nullptr, (uint64_t*)nullptr, out_status,
                        out_s, out_rank, (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)nullptr,
