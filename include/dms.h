@@ -438,6 +438,32 @@ dms_status dms_server_poll(dms_server s, int32_t wait_ms, int64_t max_out, int64
                            int8_t* out_status, uint32_t* out_sketch, int64_t* out_ids, int32_t* out_dist,
                            double* out_latency_s, int64_t* n_out);
 
+/* Make the context's device tables for k (t = ceil(k ln k) + k) now, so that
+ * later calls with this k need no allocation (dms_sketch_csr makes them on
+ * first use).  Synchronizes the stream.  Errors: DMS_EINVAL, DMS_ESPEC,
+ * DMS_ENOMEM, DMS_EHIP. */
+dms_status dms_prepare(dms_ctx ctx, int32_t k);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * dms_sketch_csr computation (same outputs, bit for bit) that calls no
+ * hipMalloc or hipFree and no allocating library routine.  Its scratch (the
+ * persistent kernel's work cursor and the largest-first size order) lives in a
+ * 16 MiB device array of the library, one per GPU, held from the library's load
+ * until the process ends.  Limits: n_sets <= 2^20 (DMS_EINVAL above); sets are
+ * not split across wavefronts (as with DMS_OPT_SPLIT_NNZ = 0, so every set must
+ * have fewer than 2^32 nonzeros).  The context's tables for k must exist
+ * (dms_prepare, or an earlier dms_sketch_csr with this k), else DMS_EINVAL.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on other streams or other contexts) race and must be ordered by the caller.
+ *   arguments as for dms_sketch_csr (out_u32, out_bits, out_status may be NULL)
+ * Errors: DMS_EINVAL, DMS_EHIP.
+ */
+dms_status dms_sketch_csr_noalloc(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                                  const double* w, int32_t k, uint32_t* out_u32, uint64_t* out_bits,
+                                  int8_t* out_status);
+
 /* Measurement support (DMS_OPT_TIMING): waits for the timed calls since the
  * last dms_kernel_time and returns the summed duration of their main kernels
  * (the persistent sketching kernel with its one-thread cursor reset, or the

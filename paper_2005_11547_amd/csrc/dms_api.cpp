@@ -227,6 +227,17 @@ struct DeviceGuard {
 
 namespace dms {
 int ctx_spec(dms_ctx c, uint32_t t, const SpecTables** out) { return spec_for(c, t, out); }
+const SpecTables* ctx_spec_cached(dms_ctx c, uint32_t t)
+{
+    auto it = c->spec.find(t);
+    return it == c->spec.end() ? nullptr : it->second;
+}
+hipStream_t ctx_stream(dms_ctx c) { return c->stream; }
+int ctx_engine(dms_ctx c) { return c->engine; }
+int ctx_order(dms_ctx c) { return c->order; }
+int ctx_resident_blocks(dms_ctx c, int mode, int k, int K) { return resident_blocks(c, mode, k, K); }
+int ctx_fail(dms_ctx c, int code, const char* msg) { return fail(c, code, "%s", msg); }
+void ctx_clear_error(dms_ctx c) { c->err.clear(); }
 int ctx_device(dms_ctx c) { return c->device; }
 int ctx_n_cu(dms_ctx c) { return c->n_cu; }
 double ctx_phi0(dms_ctx c) { return c->phi0; }
@@ -258,6 +269,14 @@ dms_status dms_create(dms_ctx* out, int device, uint64_t seed)
         return DMS_EHIP;
     }
     c->n_cu = prop.multiProcessorCount;
+    // the device's scratch of dms_sketch_csr_noalloc, looked up once per device
+    if (dms::noalloc_setup(device) != hipSuccess) {
+        (void)hipFree(c->counter);
+        (void)hipFree(c->plan);
+        (void)hipEventDestroy(c->switch_event);
+        delete c;
+        return DMS_EHIP;
+    }
     *out = c;
     return DMS_OK;
 }
@@ -623,6 +642,16 @@ dms_status dms_calibrate(dms_ctx c, int32_t kind, int32_t iters, int64_t bytes, 
     if (e != hipSuccess) return hip_fail(c, e, "calibration");
     *out_ms = ms;
     return DMS_OK;
+}
+
+dms_status dms_prepare(dms_ctx c, int32_t k)
+{
+    if (!c) return DMS_EINVAL;
+    c->err.clear();
+    if (k < 1 || k > 4096) return fail(c, DMS_EINVAL, "k = %d outside 1..4096", k);
+    DeviceGuard g(c->device);
+    const dms::SpecTables* sp = nullptr;
+    return spec_for(c, dms::t_of_k(k), &sp);
 }
 
 dms_status dms_kernel_time(dms_ctx c, double* out_ms, int64_t* out_launches)

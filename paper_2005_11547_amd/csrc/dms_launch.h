@@ -120,4 +120,15 @@ int ctx_n_cu(dms_ctx c);
 double ctx_phi0(dms_ctx c);
 double ctx_phi_max(dms_ctx c);
 int ctx_hash(dms_ctx c);
+// Accessors for the entry points defined outside dms_api.cpp.
+const SpecTables* ctx_spec_cached(dms_ctx c, uint32_t t);  // nullptr if t's tables are not made yet
+hipStream_t ctx_stream(dms_ctx c);
+int ctx_engine(dms_ctx c);
+int ctx_order(dms_ctx c);
+int ctx_resident_blocks(dms_ctx c, int mode, int k, int K);
+int ctx_fail(dms_ctx c, int code, const char* msg);
+void ctx_clear_error(dms_ctx c);
+// Looks up, once per device, the device address of dms_sketch_csr_noalloc's
+// scratch (the device must be current).
+hipError_t noalloc_setup(int device);
 }  // namespace dms

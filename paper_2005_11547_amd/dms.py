@@ -30,7 +30,7 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_server_poll", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
            "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune",
-           "dms_spec_tabulation", "dms_kernel_time"]
+           "dms_spec_tabulation", "dms_kernel_time", "dms_prepare", "dms_sketch_csr_noalloc"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -81,6 +81,8 @@ def lib():
         "dms_hamming_topk": ([vp, vp, i64, i32, vp, i64, i32, vp, vp], i32),
         "dms_sync": ([vp], i32),
         "dms_kernel_time": ([vp, P(f64), P(i64)], i32),
+        "dms_prepare": ([vp, i32], i32),
+        "dms_sketch_csr_noalloc": ([vp, i64, vp, vp, vp, i32, vp, vp, vp], i32),
         "dms_last_error": ([vp], ctypes.c_char_p),
         "dms_status_str": ([i32], ctypes.c_char_p),
         "dms_t_of_k": ([i32, P(u32)], i32),
@@ -196,6 +198,16 @@ class Context:
                                          _ptr(out_u32), _ptr(out_bits), _ptr(out_status),
                                          _ptr(out_s), _ptr(out_rank), flags, _ptr(out_counters)),
                     "dms_sketch_csr")
+
+    def dms_prepare(self, k):
+        self._stream()
+        self._check(lib().dms_prepare(self._h, k), "dms_prepare")
+
+    def dms_sketch_csr_noalloc(self, n_sets, row_ptr, idx, w, k, out_u32=None, out_bits=None, out_status=None):
+        self._stream()
+        self._check(lib().dms_sketch_csr_noalloc(self._h, n_sets, _ptr(row_ptr), _ptr(idx), _ptr(w), k,
+                                                 _ptr(out_u32), _ptr(out_bits), _ptr(out_status)),
+                    "dms_sketch_csr_noalloc")
 
     def dms_lsh_keys(self, n_sets, row_ptr, idx, w, L, K, out_keys, out_status=None, flags=0,
                      out_counters=None):
