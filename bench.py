@@ -190,18 +190,16 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=12
     search against a device-resident database of n_db sketched sets; 1% of the
     searches are near-duplicates (J = 0.9) of database rows.  The first `warm`
     seconds of the trace are excluded from the latency figures."""
-    from paper_2005_11547_amd import Server, dms
+    from paper_2005_11547_amd import Server, SketchDB
     rng = np.random.Generator(np.random.PCG64(5))
     t0 = time.time()
     db_rp, db_idx, db_w = WL.serving_sets(rng, n_db)
     log(f"serving: database of {n_db} sets generated in {time.time() - t0:.1f}s")
     d = [torch.from_numpy(a).cuda() for a in (db_rp, db_idx, db_w)]
-    words = 16
-    db_bits = torch.empty((n_db, words), dtype=torch.int64, device="cuda")
-    st = torch.empty(n_db, dtype=torch.int8, device="cuda")
+    db = SketchDB(ctx, 1024, n_db)  # 1-bit k = 1024 rows that record the context's provenance
     torch.cuda.synchronize()
     t0 = time.time()
-    ctx.dms_sketch_csr(n_db, d[0], d[1], d[2], 1024, None, db_bits, st)
+    db.append_sets(*d)
     torch.cuda.synchronize()
     log(f"serving: database sketched (k=1024, 1-bit) in {time.time() - t0:.2f}s")
     del d
@@ -218,11 +216,12 @@ def serving_run(ctx, torch, seconds, n_db, rate=50_000.0, warm=1.0, split_nnz=12
     for r, tgt in zip(planted, targets):
         rows[r] = WL.near_duplicate(rng, db_idx[db_rp[tgt]:db_rp[tgt + 1]], db_w[db_rp[tgt]:db_rp[tgt + 1]], 0.9)
     rp, idx, w = WL.csr_from_rows(rows)
-    srv = Server(ctx, db_bits, topk=10, max_batch=512, max_inflight=4, max_batch_nnz=1 << 21,
+    srv = Server(ctx, db, topk=10, max_batch=512, max_inflight=4, max_batch_nnz=1 << 21,
                  max_set_nnz=8192, split_nnz=split_nnz)
     log(f"serving: replaying {n_req} requests at {rate:.0f}/s")
     out = srv.replay(arrival, kind, k, rp, idx, w)
     srv.close()
+    db.close()
     steady = arrival >= warm
     lat = np.sort(out["latency"][steady])
     top1 = float(np.mean(out["ids"][planted, 0] == targets)) if len(planted) else None

@@ -40,6 +40,7 @@ typedef int32_t dms_status;
 #define DMS_EHIP (-2)   /* the HIP runtime reported an error */
 #define DMS_ENOMEM (-3) /* the context could not allocate its scratch space */
 #define DMS_ESPEC (-4)  /* a specification constant could not be derived exactly */
+#define DMS_EMISMATCH (-5) /* sketches made under another specification version, hash, seed or k */
 
 /* Per-set status codes written to out_status arrays. */
 #define DMS_SET_OK 0      /* sketch computed */
@@ -323,8 +324,59 @@ dms_status dms_unary_map(dms_ctx ctx, int64_t n_sets, const uint32_t* minhash, i
                          int32_t bits, int32_t* out_index, double* out_scale);
 
 /*
+ * Provenance of sketches.  Two sketches can be compared (Section 1.1: the
+ * estimators compare minhashes of the same hash functions) only if they were
+ * made under the same specification version, hash kind, seed and k.
+ */
+typedef struct {
+    int32_t spec_version; /* DMS_SPEC_VERSION */
+    int32_t hash;         /* DMS_HASH_* */
+    uint64_t seed;        /* seed of the hash keys */
+    int32_t k;            /* minhashes per sketch (bits per 1-bit row) */
+    int32_t reserved;     /* 0 */
+} dms_sketch_info;
+
+/* The provenance of the sketches this context makes at k (its seed and
+ * DMS_OPT_HASH at the time of the call).  Errors: DMS_EINVAL. */
+dms_status dms_sketch_info_of(dms_ctx ctx, int32_t k, dms_sketch_info* out);
+
+/*
+ * A device-resident database of 1-bit sketches (k bits per row, ceil(k/64)
+ * uint64 words, row id = position) that records its provenance, taken from
+ * the context at creation.  It owns its rows; the context must outlive it.
+ * dms_db_create: room for `capacity` rows (k 1..4096, capacity < 2^31).
+ *   Errors: DMS_EINVAL, DMS_ENOMEM.
+ * dms_db_append_sets: sketches n_sets CSR sets (device, as for dms_sketch_csr)
+ *   with the database's context into the next rows; out_status device int8
+ *   [n_sets] or NULL; *out_first (host, or NULL) receives the first row.
+ *   Errors: DMS_EMISMATCH (the context's hash changed since creation),
+ *   DMS_ENOMEM (capacity), and those of dms_sketch_csr.
+ * dms_db_append_bits: copies n rows of 1-bit sketches (device or host memory)
+ *   that were made under *info; DMS_EMISMATCH unless *info equals the
+ *   database's provenance; DMS_ENOMEM beyond the capacity.
+ * dms_db_info: provenance, rows held, and the device address of the rows
+ *   (any output may be NULL).
+ * dms_db_topk: dms_hamming_topk of queries (device uint64[n_q*words]) made
+ *   under *q_info against the rows held; DMS_EMISMATCH unless *q_info equals
+ *   the database's provenance.
+ * dms_db_destroy: waits for the context's stream and frees the rows.
+ * Appends and searches run on the context's stream.
+ */
+typedef struct dms_db_s* dms_db;
+dms_status dms_db_create(dms_ctx ctx, int32_t k, int64_t capacity, dms_db* out);
+dms_status dms_db_append_sets(dms_db db, int64_t n_sets, const int64_t* row_ptr, const int32_t* idx,
+                              const double* w, int8_t* out_status, int64_t* out_first);
+dms_status dms_db_append_bits(dms_db db, int64_t n, const uint64_t* bits, const dms_sketch_info* info,
+                              int64_t* out_first);
+dms_status dms_db_info(dms_db db, dms_sketch_info* info, int64_t* n_rows, const uint64_t** rows);
+dms_status dms_db_topk(dms_db db, const uint64_t* queries, int64_t n_q, const dms_sketch_info* q_info,
+                       int32_t topk, int64_t* out_ids, int32_t* out_dist);
+dms_status dms_db_destroy(dms_db db);
+
+/*
  * Hamming top-k search over 1-bit sketches (the similarity-search use of
- * Section 1.1): for every query row q, the `topk` database rows with the
+ * Section 1.1), without provenance checks (dms_db_topk checks them): for
+ * every query row q, the `topk` database rows with the
  * smallest Hamming distance, ascending by (distance, row id).
  *   db      device uint64[n_db*words]       (1-bit sketches, `words` words each)
  *   queries device uint64[n_q*words]
@@ -354,9 +406,9 @@ dms_status dms_calibrate(dms_ctx ctx, int32_t kind, int32_t iters, int64_t bytes
 
 /*
  * Serving loop (continuous batching).  A server owns, per batch slot, a HIP
- * stream, a device arena and pinned staging buffers, and scans a caller-owned,
- * device-resident database of 1-bit sketches (k = 1024, 16 words per row,
- * row id = position).  Requests are either DMS_REQ_SKETCH (k minhashes of the
+ * stream, a device arena and pinned staging buffers, and scans a sketch
+ * database (dms_db, k = 1024, 16 words per row, row id = position) whose
+ * provenance must equal the context's sketches at k = 1024.  Requests are either DMS_REQ_SKETCH (k minhashes of the
  * request's set, k in {64, 256, 1024}) or DMS_REQ_SEARCH (the set's 1-bit
  * k = 1024 sketch, then the topk database rows nearest in Hamming distance,
  * ascending by (distance, row)).  While a slot is free, the requests that have
@@ -380,11 +432,12 @@ typedef struct {
 
 typedef struct dms_server_s* dms_server;
 
-/* Create a server on ctx (the context must outlive it).  db: device
- * uint64[n_db*16], owned by the caller, read-only while the server lives.
- * Errors: DMS_EINVAL, DMS_ENOMEM, DMS_EHIP, DMS_ESPEC. */
-dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, const uint64_t* db,
-                             int64_t n_db, dms_server* out);
+/* Create a server on ctx (the context must outlive it) over the rows db holds
+ * now; the database must not be appended to or destroyed while the server
+ * lives.  Errors: DMS_EINVAL, DMS_EMISMATCH (the database was made under
+ * another specification version, hash, seed, or not at k = 1024), DMS_ENOMEM,
+ * DMS_EHIP, DMS_ESPEC. */
+dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, dms_db db, dms_server* out);
 dms_status dms_server_destroy(dms_server s);
 
 /*

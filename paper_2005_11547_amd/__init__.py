@@ -1,5 +1,5 @@
 """DartMinHash (arXiv 2005.11547) for AMD Instinct MI355X: HIP kernels behind a
 C ABI (include/dms.h) and a thin ctypes binding (``dms``)."""
 from . import dms  # noqa: F401
-from .dms import (Context, DMSError, LshIndex, Server, lib, spec_constants, spec_tabulation,  # noqa: F401
-                  t_of_k, to_device)
+from .dms import (Context, DMSError, LshIndex, Server, SketchDB, SketchInfo, lib, spec_constants,  # noqa: F401
+                  spec_tabulation, t_of_k, to_device)

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdms.so")
 SOURCES = ["dms_api.cpp", "dms_constants.cpp", "dms_plain.hip", "dms_sketch.hip", "dms_estimate.hip",
            "dms_calib.hip", "dms_search.hip", "dms_bbit.hip", "dms_index.hip", "dms_order.hip", "dms_validate.hip", "dms_noalloc.hip",
-           "dms_server.cpp"]
+           "dms_server.cpp", "dms_db.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

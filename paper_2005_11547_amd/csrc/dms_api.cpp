@@ -243,6 +243,7 @@ int ctx_n_cu(dms_ctx c) { return c->n_cu; }
 double ctx_phi0(dms_ctx c) { return c->phi0; }
 double ctx_phi_max(dms_ctx c) { return c->phi_max; }
 int ctx_hash(dms_ctx c) { return c->hash; }
+uint64_t ctx_seed(dms_ctx c) { return c->seed; }
 }  // namespace dms
 
 extern "C" {
@@ -407,13 +408,14 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     hipError_t e;
     // the flattened engine keeps its queues and k buckets in one block's LDS;
     // beyond 64 KiB the plain engine serves the call
-    if (c->engine == DMS_ENGINE_PLAIN || dms::fast_lds(dms::kModeMinhash, k, 1, 1) > 65536) {
+    const int kt = dms::minhash_tile(k);  // buckets a wave holds at once (k unless k is large)
+    if (c->engine == DMS_ENGINE_PLAIN) {
         KernelTimer tm(c);
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                      out_status, out_s, out_rank, c->phi0, c->phi_max, c->hash, x, c->stream);
         tm.done();
     } else {
-        const int64_t split = (int64_t)c->split_nnz;
+        const int64_t split = kt < k ? 0 : (int64_t)c->split_nnz;  // tiled buckets: sets are not split
         int64_t part_cap = 0;
         if (split > 0) {
             // the heavy sets are planned on the device into scratch of a fixed
@@ -435,7 +437,7 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         KernelTimer tm(c);
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
-                                          c->counter, resident_blocks(c, dms::kModeMinhash, k, 1), c->parts,
+                                          c->counter, resident_blocks(c, dms::kModeMinhash, k, kt), c->parts,
                                           part_cap, c->heavy, c->partial, split, order, c->hash, x,
                                           split > 0 ? c->plan : nullptr,
                                           split > 0 ? (const uint8_t*)c->planned : nullptr, c->stream);
@@ -694,6 +696,7 @@ const char* dms_status_str(dms_status s)
     case DMS_EHIP: return "DMS_EHIP";
     case DMS_ENOMEM: return "DMS_ENOMEM";
     case DMS_ESPEC: return "DMS_ESPEC";
+    case DMS_EMISMATCH: return "DMS_EMISMATCH";
     default: return "unknown status";
     }
 }

@@ -103,6 +103,9 @@ hipError_t launch_unary_map(int64_t n_sets, const uint32_t* v, int k, int b, int
 hipError_t launch_jaccard(int64_t n_pairs, const void* a, const void* b, int k, int format,
                           double* out, hipStream_t st);
 size_t fast_lds_bytes(int k, int waves);
+// Buckets a minhash wave of the fast engine holds at once (k, or tiles of whole
+// 64-bucket words when k buckets do not fit next to the queues).
+int minhash_tile(int k);
 hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
                              hipStream_t st);
 size_t size_order_bytes(int64_t n_sets);
@@ -120,6 +123,11 @@ int ctx_n_cu(dms_ctx c);
 double ctx_phi0(dms_ctx c);
 double ctx_phi_max(dms_ctx c);
 int ctx_hash(dms_ctx c);
+uint64_t ctx_seed(dms_ctx c);
+// Read access to a sketch database for the serving loop.
+const uint64_t* db_rows(dms_db db);
+int64_t db_count(dms_db db);
+const dms_sketch_info* db_info(dms_db db);
 // Accessors for the entry points defined outside dms_api.cpp.
 const SpecTables* ctx_spec_cached(dms_ctx c, uint32_t t);  // nullptr if t's tables are not made yet
 hipStream_t ctx_stream(dms_ctx c);

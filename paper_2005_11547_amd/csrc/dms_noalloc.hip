@@ -77,7 +77,7 @@ extern "C" dms_status dms_sketch_csr_noalloc(dms_ctx c, int64_t n_sets, const in
     const hipStream_t st = ctx_stream(c);
     if (!ptr || !fits) {
         rc = ctx_fail(c, DMS_EHIP, "no-alloc scratch unavailable on this device");
-    } else if (ctx_engine(c) == DMS_ENGINE_PLAIN || fast_lds(kModeMinhash, k, 1, 1) > 65536) {
+    } else if (ctx_engine(c) == DMS_ENGINE_PLAIN) {
         // the plain engine needs no scratch
         e = launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits, out_status, nullptr, nullptr,
                                 ctx_phi0(c), ctx_phi_max(c), ctx_hash(c), LaunchExtras{}, st);
@@ -91,7 +91,8 @@ extern "C" dms_status dms_sketch_csr_noalloc(dms_ctx c, int64_t n_sets, const in
         if (e == hipSuccess)
             e = launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits, out_status, nullptr,
                                          nullptr, ctx_phi0(c), ctx_phi_max(c), cursor,
-                                         ctx_resident_blocks(c, kModeMinhash, k, 1), nullptr, 0, nullptr, nullptr, 0,
+                                         ctx_resident_blocks(c, kModeMinhash, k, minhash_tile(k)), nullptr, 0,
+                                         nullptr, nullptr, 0,
                                          order, ctx_hash(c), LaunchExtras{}, nullptr, nullptr, st);
     }
     if (rc == DMS_OK && e != hipSuccess) rc = ctx_fail(c, DMS_EHIP, hipGetErrorString(e));

@@ -271,10 +271,19 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
 
 extern "C" {
 
-dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, const uint64_t* db,
-                             int64_t n_db, dms_server* out)
+dms_status dms_server_create(dms_ctx ctx, const dms_server_config* cfg, dms_db database, dms_server* out)
 {
-    if (!ctx || !cfg || !out || n_db < 0 || (n_db > 0 && !db)) return DMS_EINVAL;
+    if (!ctx || !cfg || !out || !database) return DMS_EINVAL;
+    {
+        dms_sketch_info mine{};
+        (void)dms_sketch_info_of(ctx, 1024, &mine);
+        const dms_sketch_info& theirs = *dms::db_info(database);
+        if (theirs.spec_version != mine.spec_version || theirs.hash != mine.hash || theirs.seed != mine.seed ||
+            theirs.k != mine.k)
+            return DMS_EMISMATCH;
+    }
+    const uint64_t* db = dms::db_rows(database);
+    const int64_t n_db = dms::db_count(database);
     const dms_server_config& C = *cfg;
     if (C.max_batch < 1 || C.max_batch > 4096 || C.max_inflight < 1 || C.max_inflight > 16 ||
         C.max_batch_nnz < 1 || C.db_words != 16 || C.topk < 1 || C.topk > 64 || C.max_set_nnz < 1 ||

@@ -173,15 +173,16 @@ __host__ __device__ constexpr size_t lsh_aux_bytes(int L)
 // through which a dart reaches the lane that holds its table.
 constexpr uint32_t kMailboxBytes = 64 * (8 + 8 + 4);
 
-// Bytes of the result area after the queues: k bucket minima (minhash), L
-// sorted lists of K darts plus their bookkeeping (LSH), a mailbox per table
+// Bytes of the result area after the queues: the minima of K buckets (minhash:
+// K is the tile of buckets a wave holds at once, k when untiled), L sorted
+// lists of K darts plus their bookkeeping (LSH), a mailbox per table
 // (register-table LSH), or the dart buffer (bottom-k).
 __host__ __device__ constexpr size_t sink_bytes(int mode, int k, int K)
 {
     return mode == kModeLshReg ? (size_t)kMailboxBytes
          : mode == kModeLsh ? (size_t)16 * k * K + lsh_aux_bytes(k)
          : mode == kModeBottomK ? (size_t)16 * bk_cap(k)
-                                : (size_t)16 * k;
+                                : (size_t)16 * K;
 }
 __host__ __device__ constexpr size_t wave_lds_bytes(int mode, int k, int K)
 {
@@ -327,7 +328,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     const int wave = threadIdx.x >> 6;
     unsigned char* wb = smem + kTablesBytes + (uint32_t)wave * (uint32_t)wave_lds_bytes(MODE, k, K);
     uint64_t* const bin_rank = reinterpret_cast<uint64_t*>(wb + kOffBins);
-    uint64_t* const bin_s = bin_rank + (LSH ? k * K : BK ? (int)bk_cap(k) : k);
+    // minhash: the wave holds the minima of buckets [tile_lo, tile_lo + K) at a
+    // time (K = k unless the buckets do not fit next to the queues)
+    uint64_t* const bin_s = bin_rank + (LSH ? k * K : BK ? (int)bk_cap(k) : K);
+    uint32_t tile_lo = 0;                       // first bucket of the current tile
+    uint32_t tile_n = MODE == kModeMinhash ? (uint32_t)K : (uint32_t)k;  // its buckets
     LshTables T;
     T.rank = bin_rank;
     T.sval = bin_s;
@@ -679,8 +684,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 bin_s[q] = s;
                             }
                             bk_count = uni(bk_count + (uint32_t)__popcll(bk));
-                        } else if (acc) {
-                            bucket_min(bin_rank, bin_s, bucket_of(s, (uint32_t)k), rb, s);
+                        } else {
+                            const uint32_t b = bucket_of(s, (uint32_t)k) - tile_lo;
+                            if (acc && b < tile_n) bucket_min(bin_rank, bin_s, b, rb, s);
                         }
                         pq_head = uni(ring_p(pq_head + m));
                         pq_count = uni(pq_count - m);
@@ -938,7 +944,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 } else if (LSH) {
                     for (int j = lane; j < k; j += kWave) filled &= T.cnt[j] >= K;
                 } else {
-                    for (int j = lane; j < k; j += kWave) filled &= bin_rank[j] != kRankEmpty;
+                    for (int j = lane; j < (int)tile_n; j += kWave) filled &= bin_rank[j] != kRankEmpty;
                 }
                 if (wave_all(filled)) break;
                 tau_prev = tau;
@@ -958,9 +964,31 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         } else if (LSH) {
             for (int j = lane; j < k; j += kWave) T.cnt[j] = 0;
         } else {
-            for (int j = lane; j < k; j += kWave) {
+            for (int j = lane; j < (int)tile_n; j += kWave) {
                 bin_rank[j] = kRankEmpty;
                 bin_s[j] = ~0ull;
+            }
+        }
+    };
+
+    // Minhash outputs of buckets [tile_lo, tile_lo + tile_n) of a set (tile_lo
+    // is a multiple of 64, so the tile owns whole words of the 1-bit sketch).
+    auto write_tile = [&](int64_t set, bool ok) {
+        for (int j = lane; j < (int)tile_n; j += kWave) {
+            const uint64_t s = ok ? bin_s[j] : ~0ull;
+            const uint64_t rb = ok ? bin_rank[j] : kRankEmpty;
+            const int64_t o = set * k + tile_lo + j;
+            if (out_u32) out_u32[o] = ok ? (uint32_t)s : 0xFFFFFFFFu;
+            if (out_s) out_s[o] = s;
+            if (out_rank) out_rank[o] = __longlong_as_double((long long)rb);
+        }
+        if (out_bits) {
+            const int words = (k + 63) / 64;
+            for (int wd = 0; wd * 64 < (int)tile_n; ++wd) {
+                const int j = wd * 64 + lane;
+                const bool bit = ok && j < (int)tile_n && (bin_s[j] & 1ull);
+                const uint64_t word = __ballot(bit);
+                if (lane == 0) out_bits[set * words + (int)(tile_lo / 64) + wd] = word;
             }
         }
     };
@@ -974,6 +1002,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         if (item >= np + n_sets) break;
         int64_t set;
         int8_t status;
+        bool tiles_written = false;  // a tiled minhash set wrote its outputs tile by tile
         n_reg = n_area = n_gen = n_rank = n_acc = n_pass = 0;
         phi_end = 0.0;
         if (MODE == kModeMinhash && item < np) {
@@ -1049,6 +1078,31 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 clear_buckets();
                 status = run(b0, b1, ri.sum, phi0, -1.0, false);
             }
+            if (MODE == kModeMinhash && K < k) {
+                // tiled buckets: the first tile's minima are in LDS; every
+                // further tile repeats the schedule for its own buckets (the
+                // minimum of each bucket is the same under any schedule)
+                wave_sync();
+                write_tile(set, status == kSetOk);
+                for (tile_lo = (uint32_t)K; tile_lo < (uint32_t)k && status == kSetOk; tile_lo += (uint32_t)K) {
+                    tile_n = min((uint32_t)K, (uint32_t)k - tile_lo);
+                    wave_sync();
+                    clear_buckets();
+                    status = run(b0, b1, ri.sum, phi0, -1.0, false);
+                    wave_sync();
+                    write_tile(set, status == kSetOk);
+                }
+                if (status != kSetOk) {
+                    // a later tile met the range limit: the set's outputs are all non-OK
+                    for (tile_lo = 0; tile_lo < (uint32_t)k; tile_lo += (uint32_t)K) {
+                        tile_n = min((uint32_t)K, (uint32_t)k - tile_lo);
+                        write_tile(set, false);
+                    }
+                }
+                tile_lo = 0;
+                tile_n = (uint32_t)K;
+                tiles_written = true;
+            }
         }
         if (DBG && out_cnt && lane == 0) {
             // counts of this wave's passes; a heavy set's parts added theirs already
@@ -1085,23 +1139,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 }
                 out_keys[set * k + l] = h;
             }
-        } else {
-            for (int j = lane; j < k; j += kWave) {
-                const uint64_t s = ok ? bin_s[j] : ~0ull;
-                const uint64_t rb = ok ? bin_rank[j] : kRankEmpty;
-                if (out_u32) out_u32[set * k + j] = ok ? (uint32_t)s : 0xFFFFFFFFu;
-                if (out_s) out_s[set * k + j] = s;
-                if (out_rank) out_rank[set * k + j] = __longlong_as_double((long long)rb);
-            }
-            if (out_bits) {
-                const int words = (k + 63) / 64;
-                for (int wd = 0; wd < words; ++wd) {
-                    const int j = wd * 64 + lane;
-                    const bool bit = ok && j < k && (bin_s[j] & 1ull);
-                    const uint64_t word = __ballot(bit);
-                    if (lane == 0) out_bits[(int64_t)set * words + wd] = word;
-                }
-            }
+        } else if (!tiles_written) {
+            write_tile(set, ok);
         }
         if (out_status && lane == 0) out_status[set] = status;
         wave_sync();  // the next set reuses this wave's LDS
@@ -1281,8 +1320,17 @@ int fast_waves(int mode, int k, int K)
     return best;
 }
 
-int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, 1); }
-size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, 1, waves); }
+// Buckets a minhash wave holds at once: all k when the minima fit next to the
+// queues in a block of at most 64 KiB, else equal tiles of whole 64-bucket words.
+int minhash_tile(int k)
+{
+    if (fast_lds(kModeMinhash, k, k, 1) <= 65536) return k;
+    const int kmax = (int)((65536 - kTablesBytes - kQueueBytes) / 16) / 64 * 64;
+    const int tiles = (k + kmax - 1) / kmax;
+    return ((k + tiles - 1) / tiles + 63) / 64 * 64;
+}
+int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, minhash_tile(k)); }
+size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, minhash_tile(k), waves); }
 
 int lsh_fast_mode(int L, int K) { return L <= kWave && K == 8 ? kModeLshReg : kModeLsh; }
 
@@ -1326,14 +1374,16 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     const unsigned long long* plan_dev, const uint8_t* planned, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int waves = fast_waves(kModeMinhash, k, 1);
-    const size_t lds = fast_lds(kModeMinhash, k, 1, waves);
+    const int kt = minhash_tile(k);
+    if (kt < k && n_parts > 0) return hipErrorInvalidValue;  // tiled buckets are not split
+    const int waves = fast_waves(kModeMinhash, k, kt);
+    const size_t lds = fast_lds(kModeMinhash, k, kt, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_parts + n_sets + waves - 1) / waves;
     if (blocks <= 0 || blocks > need) blocks = (int)(need < 1 ? 1 : need);
     const FastKernel kern = fast_kernel_for(kModeMinhash, hash, x.counters || x.repeated);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
-                       n_sets, rp, idx, w, k, 1, out_u32, out_bits, out_status, out_s, out_rank,
+                       n_sets, rp, idx, w, k, kt, out_u32, out_bits, out_status, out_s, out_rank,
                        (uint64_t*)nullptr, phi0, phi_max, counter, (const Part*)parts, n_parts,
                        (HeavySet*)heavy, partial, split, order, x.counters, x.repeated, plan_dev, planned);
     return hipGetLastError();

@@ -12,7 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdms.so")
 
-DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC = 0, -1, -2, -3, -4
+DMS_OK, DMS_EINVAL, DMS_EHIP, DMS_ENOMEM, DMS_ESPEC, DMS_EMISMATCH = 0, -1, -2, -3, -4, -5
+SPEC_VERSION = 1
 SET_OK, SET_EMPTY, SET_RANGE, SET_INVALID = 0, 1, 2, 3
 ENGINE_FAST, ENGINE_PLAIN = 0, 1
 OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH, OPT_ORDER = (
@@ -30,7 +31,9 @@ EXPORTS = ["dms_create", "dms_destroy", "dms_set_stream", "dms_set_option", "dms
            "dms_server_poll", "dms_bbit_pack",
            "dms_jaccard_est_bbit", "dms_unary_map", "dms_bottomk", "dms_jaccard_est_bottomk",
            "dms_index_build", "dms_index_sets", "dms_index_query", "dms_index_destroy", "dms_autotune",
-           "dms_spec_tabulation", "dms_kernel_time", "dms_prepare", "dms_sketch_csr_noalloc"]
+           "dms_spec_tabulation", "dms_kernel_time", "dms_prepare", "dms_sketch_csr_noalloc",
+           "dms_sketch_info_of", "dms_db_create", "dms_db_append_sets", "dms_db_append_bits", "dms_db_info",
+           "dms_db_topk", "dms_db_destroy"]
 
 REQ_SKETCH, REQ_SEARCH = 0, 1
 
@@ -43,8 +46,19 @@ class ServerConfig(ctypes.Structure):
                 ("db_words", ctypes.c_int32), ("topk", ctypes.c_int32), ("split_nnz", ctypes.c_int32)]
 
 
+class SketchInfo(ctypes.Structure):
+    """Provenance of sketches (dms_sketch_info): comparable only when equal."""
+    _fields_ = [("spec_version", ctypes.c_int32), ("hash", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.spec_version, self.hash, self.seed, self.k)
+
+
 class DMSError(RuntimeError):
-    pass
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 def lib():
@@ -88,7 +102,14 @@ def lib():
         "dms_t_of_k": ([i32, P(u32)], i32),
         "dms_spec_constants": ([u64, u32, vp, vp, vp, vp, vp], i32),
         "dms_calibrate": ([vp, i32, i32, i64, i32, vp, vp, P(f64)], i32),
-        "dms_server_create": ([vp, P(ServerConfig), vp, i64, P(vp)], i32),
+        "dms_server_create": ([vp, P(ServerConfig), vp, P(vp)], i32),
+        "dms_sketch_info_of": ([vp, i32, P(SketchInfo)], i32),
+        "dms_db_create": ([vp, i32, i64, P(vp)], i32),
+        "dms_db_append_sets": ([vp, i64, vp, vp, vp, vp, P(i64)], i32),
+        "dms_db_append_bits": ([vp, i64, vp, P(SketchInfo), P(i64)], i32),
+        "dms_db_info": ([vp, P(SketchInfo), P(i64), P(vp)], i32),
+        "dms_db_topk": ([vp, vp, i64, P(SketchInfo), i32, vp, vp], i32),
+        "dms_db_destroy": ([vp], i32),
         "dms_server_destroy": ([vp], i32),
         "dms_server_replay": ([vp, i64] + [vp] * 13, i32),
         "dms_server_submit": ([vp, i32, i32, i64, vp, vp, P(i64)], i32),
@@ -161,13 +182,21 @@ class Context:
     def _check(self, st, what):
         if st != DMS_OK:
             msg = lib().dms_last_error(self._h).decode() if getattr(self, "_h", None) else ""
-            raise DMSError(f"{what}: {lib().dms_status_str(st).decode()} {msg}")
+            raise DMSError(f"{what}: {lib().dms_status_str(st).decode()} {msg}", st)
+
+    def sketch_info(self, k: int) -> SketchInfo:
+        """Provenance of this context's sketches at k."""
+        info = SketchInfo()
+        self._check(lib().dms_sketch_info_of(self._h, k, ctypes.byref(info)), "dms_sketch_info_of")
+        return info
 
     def close(self):
-        """Destroy the context, and first every server and index built on it
-        (the C ABI requires them to go before their context)."""
+        """Destroy the context, and first every server, index and sketch
+        database built on it (the C ABI requires them to go before their
+        context)."""
         if self._h:
-            for dep in list(self._dependents):
+            # servers first: they read the databases
+            for dep in sorted(self._dependents, key=lambda d: not isinstance(d, Server)):
                 dep.close()
             lib().dms_destroy(self._h)
             self._h = ctypes.c_void_p()
@@ -430,20 +459,84 @@ class LshIndex:
             pass
 
 
-class Server:
-    """Continuous-batching serving loop (dms_server_*) over a device-resident
-    database of 1-bit k = 1024 sketches."""
+class SketchDB:
+    """Device-resident database of 1-bit sketches that records their provenance
+    (dms_db_*); appends and searches check it."""
 
-    def __init__(self, ctx: Context, db, topk=10, max_batch=256, max_inflight=4,
+    def __init__(self, ctx: Context, k: int, capacity: int):
+        self.ctx, self.k = ctx, k
+        self.words = (k + 63) // 64
+        self._h = ctypes.c_void_p()
+        self._check(lib().dms_db_create(ctx._h, k, capacity, ctypes.byref(self._h)), "dms_db_create")
+        ctx._dependents.add(self)
+
+    def _check(self, st, what):
+        if st != DMS_OK:
+            raise DMSError(f"{what}: {lib().dms_status_str(st).decode()}", st)
+
+    def info(self):
+        """(SketchInfo, rows held, device address of the rows)."""
+        info, n, rows = SketchInfo(), ctypes.c_int64(0), ctypes.c_void_p()
+        self._check(lib().dms_db_info(self._h, ctypes.byref(info), ctypes.byref(n), ctypes.byref(rows)),
+                    "dms_db_info")
+        return info, n.value, rows.value
+
+    def append_sets(self, row_ptr, idx, w):
+        """Sketch a CSR batch (device tensors) into the next rows; returns
+        (first row, int8 status tensor)."""
+        torch = self.ctx._torch
+        n = row_ptr.numel() - 1
+        st = torch.empty(n, dtype=torch.int8, device=row_ptr.device)
+        first = ctypes.c_int64(0)
+        self.ctx._stream()
+        self._check(lib().dms_db_append_sets(self._h, n, _ptr(row_ptr), _ptr(idx), _ptr(w), _ptr(st),
+                                             ctypes.byref(first)), "dms_db_append_sets")
+        return first.value, st
+
+    def append_bits(self, bits, info: SketchInfo):
+        """Copy rows of 1-bit sketches (uint64 words as int64, device or host)
+        made under `info`; returns the first row."""
+        first = ctypes.c_int64(0)
+        self.ctx._stream()
+        self._check(lib().dms_db_append_bits(self._h, bits.shape[0], _ptr(bits), ctypes.byref(info),
+                                             ctypes.byref(first)), "dms_db_append_bits")
+        return first.value
+
+    def topk(self, queries, topk: int, info: SketchInfo):
+        torch = self.ctx._torch
+        nq = queries.shape[0]
+        ids = torch.empty((nq, topk), dtype=torch.int64, device=queries.device)
+        dist = torch.empty((nq, topk), dtype=torch.int32, device=queries.device)
+        self.ctx._stream()
+        self._check(lib().dms_db_topk(self._h, _ptr(queries), nq, ctypes.byref(info), topk, _ptr(ids),
+                                      _ptr(dist)), "dms_db_topk")
+        return ids, dist
+
+    def close(self):
+        if self._h:
+            lib().dms_db_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching serving loop (dms_server_*) over a SketchDB of 1-bit
+    k = 1024 sketches made under the context's provenance."""
+
+    def __init__(self, ctx: Context, db: SketchDB, topk=10, max_batch=256, max_inflight=4,
                  max_batch_nnz=1 << 20, max_set_nnz=4096, split_nnz=128):
         import numpy as np
         self.ctx, self.db, self.topk = ctx, db, topk
         cfg = ServerConfig(max_batch, max_inflight, max_batch_nnz, max_set_nnz, 16, topk, split_nnz)
         self._h = ctypes.c_void_p()
-        st = lib().dms_server_create(ctx._h, ctypes.byref(cfg), _ptr(db), db.shape[0] if db is not None else 0,
-                                     ctypes.byref(self._h))
+        st = lib().dms_server_create(ctx._h, ctypes.byref(cfg), db._h, ctypes.byref(self._h))
         if st != DMS_OK:
-            raise DMSError(f"dms_server_create: {lib().dms_status_str(st).decode()}")
+            raise DMSError(f"dms_server_create: {lib().dms_status_str(st).decode()}", st)
         ctx._dependents.add(self)
         self._np = np
 

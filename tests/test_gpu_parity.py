@@ -226,3 +226,23 @@ def test_autotune_picks_a_candidate_and_changes_no_output(torch):
     assert c.get_option(dms.OPT_ORDER) in (0.0, 1.0)
     _check_sketch(torch, c, rp[:401], idx[:rp[400]], w[:rp[400]], 256, f"after autotune phi0={phi0} split={split}")
     c.close()
+
+
+@pytest.mark.parametrize("k", [3392, 3456, 4000, 4096])
+def test_tiled_buckets_fast_engine(torch, k):
+    """k whose buckets do not fit next to the queues: the fast engine keeps them
+    in tiles of whole words and repeats the schedule per tile; every output
+    equals the oracle's (Table 1's k = 4096 rows), with the 1-bit words of
+    every tile in place, on sets of mixed sizes and norms (retries per tile)."""
+    from paper_2005_11547_amd import Context
+    c = Context(SEED)
+    rows = []
+    rp, idx, w = WL.batch_k256(seed=12, n_sets=12)
+    rows += [(idx[rp[i]:rp[i + 1]], w[rp[i]:rp[i + 1]]) for i in range(12)]
+    for i, (l0, l1) in enumerate(((256, 1.0), (4096, 1.0), (1024, 2.0 ** 64), (1024, 2.0 ** -64), (1, 1.0))):
+        r2, i2, w2 = WL.simplex_sets(70 + i, 1, l0, l1)
+        rows.append((i2, w2))
+    rows.append((np.array([3, 9], np.int32), np.array([0.0, 0.0])))  # empty
+    rp, idx, w = WL.csr_from_rows(rows)
+    _check_sketch(torch, c, rp, idx, w, k, f"tiled k={k}")
+    c.close()

@@ -69,12 +69,14 @@ def _trace(rng, n_req, rate):
 
 @pytest.fixture(scope="module")
 def served(torch, ctx):
-    from paper_2005_11547_amd import Server
+    from paper_2005_11547_amd import Server, SketchDB, SketchInfo, dms
     rng = np.random.default_rng(55)
     n_db = 1500
     db_rp, db_idx, db_w = WL.serving_sets(rng, n_db)
     db_bits = O.sketch_csr(db_rp, db_idx, db_w, 1024, SEED)["bits"]   # the oracle builds the database
-    db = torch.from_numpy(db_bits.view(np.int64)).cuda()
+    db = SketchDB(ctx, 1024, n_db)
+    # the oracle's sketches follow specification version 1 with the mixer and SEED
+    db.append_bits(torch.from_numpy(db_bits.view(np.int64)).cuda(), SketchInfo(1, dms.HASH_MIX, SEED, 1024, 0))
     arrival, kind, k, rp, idx, w = _trace(rng, 240, 20_000.0)
     srv = Server(ctx, db, topk=10, max_batch=64, max_inflight=3)
     out = srv.replay(arrival, kind, k, rp, idx, w)
@@ -243,3 +245,62 @@ def test_closing_a_context_closes_its_server_and_index_first(torch, ctx, served)
     out = ctx.sketch(*to_device(rp, idx, w), 64)
     torch.cuda.synchronize()
     assert np.array_equal(out["u32"].cpu().numpy().view(np.uint32), O.sketch_csr(rp, idx, w, 64, SEED)["u32"])
+
+
+def test_database_provenance_is_checked(torch, ctx, served):
+    """A database, its appends and its queries carry the (specification version,
+    hash, seed, k) they were made under: mismatches are refused, matching
+    sketches from the library and from the oracle are interchangeable."""
+    from paper_2005_11547_amd import Context, Server, SketchDB, SketchInfo, dms, to_device
+    rng = np.random.default_rng(56)
+    rp, idx, w = WL.serving_sets(rng, 50)
+    d = to_device(rp, idx, w)
+    ref = O.sketch_csr(rp, idx, w, 1024, SEED)
+    mine = ctx.sketch_info(1024)
+    assert mine.as_tuple() == (dms.SPEC_VERSION, dms.HASH_MIX, SEED, 1024)
+    db = SketchDB(ctx, 1024, 200)
+    first, st = db.append_sets(*d)
+    db.append_bits(torch.from_numpy(ref["bits"].view(np.int64)).cuda(), mine)
+    info, n, rows = db.info()
+    assert first == 0 and n == 100 and info.as_tuple() == mine.as_tuple()
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), ref["status"])
+    q = torch.from_numpy(ref["bits"][:7].view(np.int64)).cuda()
+    ids, dist = db.topk(q, 3, mine)
+    torch.cuda.synchronize()
+    assert (dist.cpu().numpy()[:, 0] == 0).all()  # each query finds its own two copies at distance 0
+    assert (ids.cpu().numpy()[:, :2] == np.stack([np.arange(7), np.arange(7) + 50], 1)).all()
+    for bad in (SketchInfo(2, dms.HASH_MIX, SEED, 1024, 0), SketchInfo(1, dms.HASH_TAB, SEED, 1024, 0),
+                SketchInfo(1, dms.HASH_MIX, SEED + 1, 1024, 0), SketchInfo(1, dms.HASH_MIX, SEED, 256, 0)):
+        with pytest.raises(dms.DMSError) as e:
+            db.append_bits(q, bad)
+        assert e.value.code == dms.DMS_EMISMATCH
+        with pytest.raises(dms.DMSError):
+            db.topk(q, 3, bad)
+    with pytest.raises(dms.DMSError):  # past the capacity
+        db.append_bits(torch.zeros((101, 16), dtype=torch.int64, device="cuda"), mine)
+    # a server accepts only a database of its context's sketches at k = 1024
+    other = Context(SEED + 1)
+    with pytest.raises(dms.DMSError) as e:
+        Server(other, db, topk=10, max_batch=8, max_inflight=1)
+    assert e.value.code == dms.DMS_EMISMATCH
+    small = SketchDB(ctx, 256, 4)
+    with pytest.raises(dms.DMSError):
+        Server(ctx, small, topk=10, max_batch=8, max_inflight=1)
+    tab = Context(SEED)
+    tab.set_option(dms.OPT_HASH, dms.HASH_TAB)
+    with pytest.raises(dms.DMSError):
+        Server(tab, db, topk=10, max_batch=8, max_inflight=1)
+    # a database made before the context's hash changed refuses further appends
+    ctx2 = Context(SEED)
+    db2 = SketchDB(ctx2, 1024, 60)
+    ctx2.set_option(dms.OPT_HASH, dms.HASH_TAB)
+    with pytest.raises(dms.DMSError) as e:
+        db2.append_sets(*d)
+    assert e.value.code == dms.DMS_EMISMATCH
+    srv = Server(ctx, db, topk=10, max_batch=8, max_inflight=1)
+    srv.close()
+    for c in (other, tab, ctx2):
+        c.close()
+    small.close()
+    db.close()
