@@ -386,46 +386,53 @@ def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
     return res
 
 
-def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5):
-    """Estimates and fingerprints of the main batch's sketches: the u32 and
-    1-bit estimates over row pairs (2i, 2i+1), b-bit packing, the b-bit
-    estimate over the same pairs, and the unary map.  All are HBM bound: GB/s
-    of their algorithmic bytes against the 8 TB/s peak, each checked bit for
-    bit on a row sample."""
+def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5, big_pairs_1bit=1 << 24,
+                     big_pairs_bbit=1 << 21):
+    """Estimates and fingerprints, all HBM bound, each moving about 1 GB or
+    more per call: the u32 estimate over the main batch's row pairs (2i, 2i+1),
+    b-bit packing and the unary map of the main batch's minhashes, and the
+    1-bit and b-bit estimates over 2^24 and 2^21 pairs of random rows (their
+    cost does not depend on the values).  GB/s of each call's algorithmic bytes
+    against the 8 TB/s peak, each checked bit for bit on a sample."""
     from paper_2005_11547_amd import dms
     from oracle import oracle as O
     n = out_u32.shape[0]
     words = (k * bits + 63) // 64
     packed = torch.empty((n, words), dtype=torch.int64, device="cuda")
     n_pairs = n // 2
-    est = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
     uidx = torch.empty((n, k), dtype=torch.int32, device="cuda")
-    pa, pb = packed[0:2 * n_pairs:2], packed[1:2 * n_pairs:2]
-    ea, eb = pa.contiguous(), pb.contiguous()
     ua_all, ub_all = out_u32[0:2 * n_pairs:2].contiguous(), out_u32[1:2 * n_pairs:2].contiguous()
-    ba_all, bb_all = out_bits[0:2 * n_pairs:2].contiguous(), out_bits[1:2 * n_pairs:2].contiguous()
     est_u32 = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
-    est_1bit = torch.empty(n_pairs, dtype=torch.float64, device="cuda")
     bwords = (k + 63) // 64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2005_11547)
+
+    def rand_rows(m, w):
+        return torch.randint(-2 ** 63, 2 ** 63 - 1, (m, w), dtype=torch.int64, device="cuda", generator=g)
+
+    ba, bb = rand_rows(big_pairs_1bit, bwords), rand_rows(big_pairs_1bit, bwords)
+    pa, pb = rand_rows(big_pairs_bbit, words), rand_rows(big_pairs_bbit, words)
+    est_1bit = torch.empty(big_pairs_1bit, dtype=torch.float64, device="cuda")
+    est = torch.empty(big_pairs_bbit, dtype=torch.float64, device="cuda")
     runs = {
         "estimate_u32": (lambda: ctx.dms_jaccard_est(n_pairs, ua_all, ub_all, k, dms.FMT_U32, est_u32),
                          n_pairs * (8.0 * k + 8.0)),
-        "estimate_1bit": (lambda: ctx.dms_jaccard_est(n_pairs, ba_all, bb_all, k, dms.FMT_1BIT, est_1bit),
-                          n_pairs * (16.0 * bwords + 8.0)),
+        "estimate_1bit": (lambda: ctx.dms_jaccard_est(big_pairs_1bit, ba, bb, k, dms.FMT_1BIT, est_1bit),
+                          big_pairs_1bit * (16.0 * bwords + 8.0)),
         "pack": (lambda: ctx.dms_bbit_pack(n, out_u32, k, bits, packed), n * (4.0 * k + 8.0 * words)),
-        "estimate": (lambda: ctx.dms_jaccard_est_bbit(n_pairs, ea, eb, k, bits, est),
-                     n_pairs * (16.0 * words + 8.0)),
+        "estimate": (lambda: ctx.dms_jaccard_est_bbit(big_pairs_bbit, pa, pb, k, bits, est),
+                     big_pairs_bbit * (16.0 * words + 8.0)),
         "unary_map": (lambda: ctx.dms_unary_map(n, out_u32, k, bits, uidx), n * 8.0 * k),
     }
-    res = {"bits": bits, "n_sets": n, "k": k, "pairs": "rows (2i, 2i + 1)"}
+    res = {"bits": bits, "n_sets": n, "k": k,
+           "pairs": f"u32: rows (2i, 2i + 1) of the batch; 1-bit: {big_pairs_1bit} and b-bit: {big_pairs_bbit} "
+                    f"pairs of random rows"}
     # each timed call starts after 512 MiB of unrelated writes, so its inputs come
     # from HBM, not from the 256 MB last-level cache
     flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.int64, device="cuda")
     for name, (fn, nbytes) in runs.items():
         fn()
         torch.cuda.synchronize()
-        if name == "pack":  # the estimate reads the packed rows
-            ea.copy_(packed[0:2 * n_pairs:2]); eb.copy_(packed[1:2 * n_pairs:2])
         ms = 0.0
         for rep in range(steps):
             flush.fill_(rep)
@@ -436,24 +443,24 @@ def fingerprint_runs(ctx, torch, out_u32, out_bits, k, bits=8, steps=5):
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1) / steps
         gbs = nbytes / (ms * 1e-3) / 1e9
-        res[name] = {"ms": ms, "gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+        res[name] = {"ms": ms, "gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS, "bytes": nbytes}
     rows = np.linspace(0, n_pairs - 1, 200).astype(np.int64)
+    sel = torch.from_numpy(rows).cuda()
     ra = torch.from_numpy(2 * rows).cuda()
     ua = out_u32[ra].cpu().numpy().view(np.uint32)
     ub = out_u32[ra + 1].cpu().numpy().view(np.uint32)
-    ref_pa = O.bbit_pack(ua, bits)
-    ok = np.array_equal(packed[ra].cpu().numpy().view(np.uint64), ref_pa)
-    ok &= np.array_equal(est[torch.from_numpy(rows).cuda()].cpu().numpy(),
-                         O.jaccard_est_bbit(ref_pa, O.bbit_pack(ub, bits), k, bits))
+    ok = np.array_equal(packed[ra].cpu().numpy().view(np.uint64), O.bbit_pack(ua, bits))
     ok &= np.array_equal(uidx[ra].cpu().numpy(), O.unary_map(ua, bits)[0])
-    sel = torch.from_numpy(rows).cuda()
     ok &= np.array_equal(est_u32[sel].cpu().numpy(), O.jaccard_est_u32(ua, ub))
-    wa = out_bits[ra].cpu().numpy().view(np.uint64)
-    wb = out_bits[ra + 1].cpu().numpy().view(np.uint64)
-    ok &= np.array_equal(est_1bit[sel].cpu().numpy(), O.jaccard_est_1bit(wa, wb, k))
-    res["bit_exact_sample"] = {"rows_checked": int(len(rows)), "exact": bool(ok)}
+    r1 = torch.from_numpy(np.linspace(0, big_pairs_1bit - 1, 200).astype(np.int64)).cuda()
+    ok &= np.array_equal(est_1bit[r1].cpu().numpy(), O.jaccard_est_1bit(ba[r1].cpu().numpy().view(np.uint64),
+                                                                        bb[r1].cpu().numpy().view(np.uint64), k))
+    r2 = torch.from_numpy(np.linspace(0, big_pairs_bbit - 1, 200).astype(np.int64)).cuda()
+    ok &= np.array_equal(est[r2].cpu().numpy(), O.jaccard_est_bbit(pa[r2].cpu().numpy().view(np.uint64),
+                                                                    pb[r2].cpu().numpy().view(np.uint64), k, bits))
+    res["bit_exact_sample"] = {"rows_checked": 200, "exact": bool(ok)}
     log(f"fingerprints: {res}")
-    del packed, est, uidx, ea, eb, ua_all, ub_all, ba_all, bb_all, est_u32, est_1bit, flush
+    del packed, est, uidx, ua_all, ub_all, ba, bb, pa, pb, est_u32, est_1bit, flush
     return res
 
 
@@ -557,6 +564,72 @@ def table1_run(ctx, torch, cpu_seconds=2.0):
     return rows
 
 
+def cached(name, gen, cache_dir):
+    """A workload's CSR arrays, generated once and kept in cache_dir (if given)."""
+    if not cache_dir:
+        return gen()
+    os.makedirs(cache_dir, exist_ok=True)
+    path = os.path.join(cache_dir, name + ".npz")
+    if not os.path.exists(path):
+        rp, idx, w = gen()
+        np.savez(path, rp=rp, idx=idx, w=w)
+    z = np.load(path)
+    return z["rp"], z["idx"], z["w"]
+
+
+def kernels_once(cache_dir):
+    """Every benched kernel once at its benched size, nothing else (for counter
+    runs under rocprofv3): the k = 256 batch sketch, the uneven k = 1024
+    sketch, the (64,8) LSH keys, bottom-k (k = 256), the estimators, b-bit pack,
+    unary map and both copy calibration kernels."""
+    import torch
+    from paper_2005_11547_amd import Context, dms, to_device
+    ctx = Context(WL.HASH_SEED)
+    done = []
+    rp, idx, w = cached("batch_k256", WL.batch_k256, cache_dir)
+    n = len(rp) - 1
+    d = to_device(rp, idx, w)
+    u32 = torch.empty((n, 256), dtype=torch.int32, device="cuda")
+    bits = torch.empty((n, 4), dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.int8, device="cuda")
+    ctx.dms_sketch_csr(n, *d, 256, u32, bits, st)
+    bs = torch.empty((n, 256), dtype=torch.int64, device="cuda")
+    br = torch.empty((n, 256), dtype=torch.float64, device="cuda")
+    ctx.dms_bottomk(n, *d, 256, bs, br, st)
+    torch.cuda.synchronize()
+    done += ["sketch batch_k256", "bottomk batch_k256"]
+    del bs, br, d
+    fp = fingerprint_runs(ctx, torch, u32, bits, 256, steps=1)
+    done += [k for k in fp if isinstance(fp[k], dict) and "gbs" in fp[k]]
+    del u32, bits
+    rp, idx, w = cached("lsh_L64K8", WL.lsh_L64K8, cache_dir)
+    n = len(rp) - 1
+    d = to_device(rp, idx, w)
+    keys = torch.empty((n, 64), dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.int8, device="cuda")
+    ctx.dms_lsh_keys(n, *d, 64, 8, keys, st)
+    torch.cuda.synchronize()
+    done.append("lsh_keys lsh_L64K8")
+    del d, keys
+    rp, idx, w = cached("uneven_k1024", WL.uneven_k1024, cache_dir)
+    n = len(rp) - 1
+    d = to_device(rp, idx, w)
+    u32 = torch.empty((n, 1024), dtype=torch.int32, device="cuda")
+    bits = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.int8, device="cuda")
+    ctx.dms_sketch_csr(n, *d, 1024, u32, bits, st)
+    torch.cuda.synchronize()
+    done.append("sketch uneven_k1024")
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    ctx.calibrate(2, 1, n_cu * 8, src, dst, nb)
+    ctx.calibrate(3, 1, n_cu * 8, src, dst, nb)
+    done.append("copy calibration (plain, four in flight), 1 GiB")
+    print(json.dumps({"kernels_once": done}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -587,6 +660,10 @@ def main():
                     help="also time the k=1024 and LSH workloads (0 disables)")
     ap.add_argument("--copy-calibration", type=int, default=1 << 30,
                     help="bytes moved by the stream-copy calibration kernel (0 disables it)")
+    ap.add_argument("--kernels-once", action="store_true",
+                    help="run every benched kernel once at its benched size and exit (for counter runs)")
+    ap.add_argument("--data-cache", default="",
+                    help="directory that keeps generated workloads between runs (--kernels-once)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -597,6 +674,10 @@ def main():
 
     import torch
     from paper_2005_11547_amd import Context, dms, to_device
+
+    if args.kernels_once:
+        kernels_once(args.data_cache)
+        return
 
     if args.table1:
         ctx = Context(WL.HASH_SEED)
@@ -774,10 +855,15 @@ def main():
         src = torch.empty(nb // 8, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
         src.fill_(1)
-        ctx.calibrate(2, 1, n_cu * 8, src, dst, nb)  # warm-up
-        ms_copy = min(ctx.calibrate(2, 1, n_cu * 8, src, dst, nb) for _ in range(3))
-        result["roofline"]["hbm_copy_gbs"] = 2.0 * nb / (ms_copy * 1e-3) / 1e9
-        log(f"stream copy of {nb} bytes: {result['roofline']['hbm_copy_gbs']:.0f} GB/s (read+write)")
+        copy = {}
+        for kind, name in ((2, "plain"), (3, "four_in_flight_streaming")):
+            for blocks in (n_cu * 8, n_cu * 32):
+                ctx.calibrate(kind, 1, blocks, src, dst, nb)  # warm-up
+                ms_copy = min(ctx.calibrate(kind, 1, blocks, src, dst, nb) for _ in range(3))
+                copy[f"{name}_{blocks}_blocks"] = 2.0 * nb / (ms_copy * 1e-3) / 1e9
+        result["roofline"]["hbm_copy_gbs"] = max(copy.values())
+        result["roofline"]["hbm_copy_variants_gbs"] = copy
+        log(f"stream copy of {nb} bytes (read+write GB/s): {copy}")
         del src, dst
     if args.secondary and args.workload == "batch_k256":
         fp = fingerprint_runs(ctx, torch, out_u32, out_bits, k)

@@ -397,6 +397,8 @@ dms_status dms_hamming_topk(dms_ctx ctx, const uint64_t* db, int64_t n_db, int32
  * kind 2: copy `bytes` (multiple of 16) from device buffer a to device buffer b
  *         with a grid-stride loop: HBM bandwidth and the reference for scaling
  *         the FETCH_SIZE / WRITE_SIZE counters.
+ * kind 3: the same copy with four 16-byte loads in flight per thread and
+ *         streaming (non-temporal) stores.
  * a must hold at least 8 bytes for kinds 0 and 1.  Blocks until the kernel
  * is done and stores its duration in *out_ms (HIP events on the context's
  * stream).  Errors: DMS_EINVAL, DMS_EHIP.

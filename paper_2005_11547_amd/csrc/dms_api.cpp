@@ -626,8 +626,8 @@ dms_status dms_calibrate(dms_ctx c, int32_t kind, int32_t iters, int64_t bytes, 
 {
     if (!c) return DMS_EINVAL;
     c->err.clear();
-    if (kind < 0 || kind > 2 || iters < 1 || blocks < 1 || !a || !out_ms ||
-        (kind == 2 && (!b || bytes < 16 || bytes % 16)))
+    if (kind < 0 || kind > 3 || iters < 1 || blocks < 1 || !a || !out_ms ||
+        (kind >= 2 && (!b || bytes < 16 || bytes % 16)))
         return fail(c, DMS_EINVAL, "bad calibration arguments");
     DeviceGuard g(c->device);
     hipEvent_t e0, e1;

@@ -5,7 +5,8 @@
 //   - full-rate integer throughput: chains of 32-bit xor/add (v_xor_b32,
 //     v_add_u32), the chip's integer VALU issue peak;
 //   - stream copy: HBM read+write bandwidth, and the reference for scaling the
-//     FETCH_SIZE / WRITE_SIZE counters.
+//     FETCH_SIZE / WRITE_SIZE counters (plain, and with four loads in flight
+//     per thread and streaming stores).
 #include "dms_device.h"
 
 namespace dms {
@@ -55,6 +56,27 @@ __global__ void __launch_bounds__(256) calib_copy_kernel(const uint4* __restrict
         dst[i] = src[i];
 }
 
+// The same copy with four 16-byte loads in flight per thread before its four
+// stores (each of the four coalesced across the block), and stores that
+// bypass the caches on the way to HBM; the tail is copied one vector at a time.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) calib_copy4_kernel(const u32x4* __restrict__ src,
+                                                          u32x4* __restrict__ dst, int64_t n)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * 4;
+    const int64_t full = n / step * step;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; base < full; base += step) {
+        u32x4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = src[base + j * blockDim.x];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(v[j], &dst[base + j * blockDim.x]);
+    }
+    for (int64_t i = full + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int blocks, hipStream_t st)
 {
     switch (kind) {
@@ -64,9 +86,13 @@ hipError_t calib_run(int kind, int iters, void* a, void* b, int64_t bytes, int b
     case 1:
         hipLaunchKernelGGL(calib_int_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t*)a, iters);
         break;
-    default:
+    case 2:
         hipLaunchKernelGGL(calib_copy_kernel, dim3(blocks), dim3(256), 0, st, (const uint4*)a,
                            (uint4*)b, bytes / 16);
+        break;
+    default:
+        hipLaunchKernelGGL(calib_copy4_kernel, dim3(blocks), dim3(256), 0, st, (const u32x4*)a,
+                           (u32x4*)b, bytes / 16);
         break;
     }
     return hipGetLastError();

@@ -993,8 +993,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         }
     };
 
-    // parts of a device plan: their count was written by the planning kernel
-    const int64_t np = plan_dev ? (int64_t)plan_dev[1] : n_parts;
+    // parts of a device plan: the planning kernel's cursor, at most the capacity
+    const int64_t np = plan_dev ? min((int64_t)plan_dev[1], n_parts) : n_parts;
     for (;;) {
         unsigned long long got = 0;
         if (lane == 0) got = atomicAdd(next_set, 1ull);
@@ -1008,6 +1008,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         if (MODE == kModeMinhash && item < np) {
             // ---- one part of a heavy set ----
             const Part pt = parts[item];
+            if (pt.set < 0) continue;  // an empty slot of the device plan
             HeavySet* hs = heavy + pt.heavy;
             set = pt.set;
             const int64_t b0 = rp[set], b1 = rp[set + 1];
@@ -1170,11 +1171,13 @@ DMS_FAST_KERNELS(kModeLshReg, kHashTab)
 #undef DMS_FAST_KERNEL
 
 // Device-side planning of the heavy sets.  plan[0] counts the heavy sets that
-// got parts, plan[1] their parts; both start at 0 (plan_reset_kernel).  A set
-// above the split threshold reserves its parts with a compare-and-swap on
-// plan[1] so that the reserved ranges have no holes; a set whose parts would
-// pass the capacity gets none and is sketched whole by one wave.  planned[s]
-// tells the main kernel which sets its parts serve.
+// got parts, plan[1] is the parts cursor; both start at 0 (plan_reset_kernel).
+// A set above the split threshold reserves its parts with one atomic add on
+// the cursor (no retry loop: many heavy sets would serialize on it); a set
+// whose range passes the capacity gets no parts and is sketched whole by one
+// wave, and the slots of its range below the capacity become empty parts
+// (set -1) that the main kernel skips, so [0, min(cursor, capacity)) holds no
+// unwritten slot.  planned[s] tells the main kernel which sets its parts serve.
 __global__ void plan_reset_kernel(unsigned long long* plan)
 {
     if (threadIdx.x < 8) plan[threadIdx.x] = 0ull;
@@ -1190,17 +1193,16 @@ plan_kernel(int64_t n_sets, const int64_t* __restrict__ rp, int64_t split, int64
     uint8_t mine = 0;
     if (nnz > split) {
         const int64_t P = (nnz + split - 1) / split;
-        unsigned long long old = __hip_atomic_load(&plan[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t base = -1;
-        while ((int64_t)old + P <= part_cap && P < 0x7FFFFFFF) {
-            const unsigned long long seen = atomicCAS(&plan[1], old, old + (unsigned long long)P);
-            if (seen == old) {
-                base = (int64_t)old;
-                break;
+        const int64_t base = P < part_cap ? (int64_t)atomicAdd(&plan[1], (unsigned long long)P) : part_cap;
+        if (base + P > part_cap) {
+            for (int64_t p = base; p < part_cap; ++p) {
+                Part pt;
+                pt.set = -1;  // an empty slot of a range that did not fit
+                pt.heavy = 0;
+                pt.index = 0;
+                parts[p] = pt;
             }
-            old = seen;
-        }
-        if (base >= 0) {
+        } else {
             if (out_cnt) {  // the parts of the set add their counts
                 for (int q = 0; q < kCounterWords; ++q) out_cnt[s * kCounterWords + q] = 0;
             }
