@@ -77,6 +77,14 @@ typedef int32_t dms_status;
                                device before the main launch), 0 in input order.  Batches of
                                2^31 sets or more always run in input order. */
 
+#define DMS_OPT_WAVES 9     /* dms_sketch_csr, fast engine: waves per block, 1..4 (0, the default:
+                               the count that keeps the most waves resident in a CU's LDS) */
+#define DMS_OPT_TILE 10     /* dms_sketch_csr, fast engine: buckets a wave holds at once, a multiple
+                               of 64 below k; the schedule then runs once per tile of buckets (same
+                               outputs, more passes, less LDS per wave).  0 (default): all k when
+                               they fit next to the queues in 64 KiB, else the fewest equal tiles.
+                               A call whose choice of tile and waves does not fit 64 KiB of LDS
+                               returns DMS_EINVAL. */
 #define DMS_OPT_TIMING 8    /* 1: bracket the main kernel of every dms_sketch_csr, dms_lsh_keys and
                                dms_bottomk call with HIP events on the context's stream (read
                                and reset by dms_kernel_time); 0 (default): no events */
@@ -170,8 +178,9 @@ dms_status dms_sketch_csr(dms_ctx ctx, int64_t n_sets, const int64_t* row_ptr,
  * (its first min(n_sets, 2^28/k) rows, so the rows should be in no particular
  * order) under candidate schedules -- first phi in {1, 1.15, 1.3, 1.5, 1.8},
  * then split thresholds in {0, 1024, 4096, 16384}, then both DMS_OPT_ORDER
- * values -- and sets DMS_OPT_PHI0, DMS_OPT_SPLIT_NNZ and DMS_OPT_ORDER on the
- * context to the fastest.  Outputs never depend on
+ * values, then waves per block 1..4 and half the automatic bucket tile -- and
+ * sets DMS_OPT_PHI0, DMS_OPT_SPLIT_NNZ, DMS_OPT_ORDER, DMS_OPT_WAVES and
+ * DMS_OPT_TILE on the context to the fastest.  Outputs never depend on
  * either (Theorem 1's output is independent of the schedule; parts merge
  * exactly).  Synchronizes the stream; allocates and frees its own buffers.
  *   out_phi0, out_split: host double* or NULL, receive the chosen values

@@ -45,6 +45,8 @@ struct dms_ctx_s {
     double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
     int hash = dms::kHashMix;   // DMS_HASH_*
     int order = 1;              // DMS_OPT_ORDER: largest sets first
+    int waves = 0;              // DMS_OPT_WAVES: waves per block of the minhash kernel (0: automatic)
+    int tile = 0;               // DMS_OPT_TILE: buckets per tile of the minhash kernel (0: automatic)
     void* order_buf = nullptr;  // its keys, values and sort scratch
     size_t order_bytes = 0;
     double phi_max = 1048576.0;
@@ -125,10 +127,11 @@ dms_status grow(dms_ctx c, void** buf, size_t* have, size_t need)
     return DMS_OK;
 }
 
-// Blocks of the persistent kernel that fit on the device at once.
-int resident_blocks(dms_ctx c, int mode, int k, int K)
+// Blocks of the persistent kernel that fit on the device at once (blocks of
+// `waves` waves, or of the automatic choice when 0).
+int resident_blocks(dms_ctx c, int mode, int k, int K, int waves = 0)
 {
-    const int waves = dms::fast_waves(mode, k, K);
+    if (waves <= 0) waves = dms::fast_waves(mode, k, K);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dms::fast_kernel_address(mode, c->hash), 64 * waves,
                                                      dms::fast_lds(mode, k, K, waves)) != hipSuccess)
@@ -351,6 +354,16 @@ dms_status dms_set_option(dms_ctx c, int32_t opt, double v)
         if (v != 0.0 && v != 1.0) return fail(c, DMS_EINVAL, "timing must be 0 or 1");
         c->timing = v != 0.0;
         return DMS_OK;
+    case DMS_OPT_WAVES:
+        if (v != 0.0 && v != 1.0 && v != 2.0 && v != 3.0 && v != 4.0)
+            return fail(c, DMS_EINVAL, "waves per block must be 0 (automatic) or 1..4");
+        c->waves = (int)v;
+        return DMS_OK;
+    case DMS_OPT_TILE:
+        if (!(v >= 0.0) || v > 4096.0 || v != (double)(int)v || ((int)v % 64 != 0))
+            return fail(c, DMS_EINVAL, "buckets per tile must be 0 (automatic) or a multiple of 64 up to 4096");
+        c->tile = (int)v;
+        return DMS_OK;
     case DMS_OPT_SPLIT_NNZ:
         if (!(v >= 0.0) || v > 1e12 || v != (double)(int64_t)v)
             return fail(c, DMS_EINVAL, "split threshold must be a non-negative integer");
@@ -384,6 +397,8 @@ dms_status dms_get_option(dms_ctx c, int32_t opt, double* v)
     case DMS_OPT_HASH: *v = c->hash; return DMS_OK;
     case DMS_OPT_ORDER: *v = c->order; return DMS_OK;
     case DMS_OPT_TIMING: *v = c->timing ? 1.0 : 0.0; return DMS_OK;
+    case DMS_OPT_WAVES: *v = c->waves; return DMS_OK;
+    case DMS_OPT_TILE: *v = c->tile; return DMS_OK;
     default: return fail(c, DMS_EINVAL, "unknown option %d", opt);
     }
 }
@@ -408,7 +423,10 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
     hipError_t e;
     // the flattened engine keeps its queues and k buckets in one block's LDS;
     // beyond 64 KiB the plain engine serves the call
-    const int kt = dms::minhash_tile(k);  // buckets a wave holds at once (k unless k is large)
+    const int kt = dms::minhash_tile_for(k, c->tile);  // buckets a wave holds at once (k unless k is large)
+    const int waves = kt > 0 ? dms::minhash_waves_for(k, kt, c->waves) : 0;
+    if (c->engine != DMS_ENGINE_PLAIN && (kt <= 0 || waves <= 0))
+        return fail(c, DMS_EINVAL, "DMS_OPT_TILE / DMS_OPT_WAVES do not fit a block's 64 KiB of LDS at k = %d", k);
     if (c->engine == DMS_ENGINE_PLAIN) {
         KernelTimer tm(c);
         e = dms::launch_sketch_plain(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
@@ -437,10 +455,10 @@ dms_status dms_sketch_csr(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, con
         KernelTimer tm(c);
         e = dms::launch_sketch_fast_split(sp, n_sets, row_ptr, idx, w, k, out_u32, out_bits,
                                           out_status, out_s, out_rank, c->phi0, c->phi_max,
-                                          c->counter, resident_blocks(c, dms::kModeMinhash, k, kt), c->parts,
+                                          c->counter, resident_blocks(c, dms::kModeMinhash, k, kt, waves), c->parts,
                                           part_cap, c->heavy, c->partial, split, order, c->hash, x,
                                           split > 0 ? c->plan : nullptr,
-                                          split > 0 ? (const uint8_t*)c->planned : nullptr, c->stream);
+                                          split > 0 ? (const uint8_t*)c->planned : nullptr, kt, waves, c->stream);
         tm.done();
     }
     if (e != hipSuccess) return hip_fail(c, e, "sketch launch");
@@ -978,9 +996,9 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         return best;
     };
     const double keep_phi0 = c->phi0, keep_split = c->split_nnz;
-    const int keep_order = c->order;
+    const int keep_order = c->order, keep_waves = c->waves, keep_tile = c->tile;
     double best_phi0 = keep_phi0, best_split = keep_split;
-    int best_order = keep_order;
+    int best_order = keep_order, best_waves = keep_waves, best_tile = keep_tile;
     if (rc == DMS_OK) {
         // coordinate search: the first phi, then the split threshold
         const double phis[] = {1.0, 1.15, 1.3, 1.5, 1.8};
@@ -999,7 +1017,31 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
         // then the order in which waves take the sets
         c->order = 1 - keep_order;
         const float ms = trial(best_phi0, best_split);
-        if (ms < best) best_order = c->order;
+        if (ms < best) {
+            best = ms;
+            best_order = c->order;
+        }
+        c->order = best_order;
+        // then the block shape: waves per block, and buckets per tile (half the
+        // automatic tile, twice the passes, more waves resident)
+        const int auto_tile = dms::minhash_tile(k);
+        const int tiles[2] = {0, auto_tile >= 128 ? (auto_tile / 2 + 63) / 64 * 64 : 0};
+        for (int ti = 0; ti < 2 && rc == DMS_OK; ++ti) {
+            if (ti == 1 && (tiles[1] == 0 || dms::minhash_tile_for(k, tiles[1]) <= 0)) continue;
+            for (int wv = 0; wv <= 4 && rc == DMS_OK; ++wv) {
+                if (ti == 0 && wv == 0) continue;  // the automatic shape, timed above
+                const int kt = dms::minhash_tile_for(k, tiles[ti]);
+                if (wv > 0 && dms::minhash_waves_for(k, kt, wv) <= 0) continue;
+                c->tile = tiles[ti];
+                c->waves = wv;
+                const float mt = trial(best_phi0, best_split);
+                if (mt < best) {
+                    best = mt;
+                    best_tile = tiles[ti];
+                    best_waves = wv;
+                }
+            }
+        }
     }
     (void)hipFree(out);
     (void)hipFree(st);
@@ -1008,6 +1050,8 @@ dms_status dms_autotune(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const
     c->phi0 = rc == DMS_OK ? best_phi0 : keep_phi0;
     c->split_nnz = rc == DMS_OK ? best_split : keep_split;
     c->order = rc == DMS_OK ? best_order : keep_order;
+    c->waves = rc == DMS_OK ? best_waves : keep_waves;
+    c->tile = rc == DMS_OK ? best_tile : keep_tile;
     if (rc != DMS_OK) return rc;
     if (out_phi0) *out_phi0 = best_phi0;
     if (out_split) *out_split = best_split;

@@ -72,7 +72,8 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
                                     const uint32_t* order, int hash, const LaunchExtras& x,
-                                    const unsigned long long* plan_dev, const uint8_t* planned, hipStream_t st);
+                                    const unsigned long long* plan_dev, const uint8_t* planned, int kt_opt,
+                                    int waves_opt, hipStream_t st);
 size_t plan_part_bytes();
 size_t plan_heavy_bytes();
 // Device-side plan of the heavy sets for launch_sketch_fast_split: resets
@@ -106,6 +107,10 @@ size_t fast_lds_bytes(int k, int waves);
 // Buckets a minhash wave of the fast engine holds at once (k, or tiles of whole
 // 64-bucket words when k buckets do not fit next to the queues).
 int minhash_tile(int k);
+// Tile and waves per block for the DMS_OPT_TILE / DMS_OPT_WAVES values (0:
+// automatic); 0 when the choice does not fit a block's 64 KiB of LDS.
+int minhash_tile_for(int k, int t);
+int minhash_waves_for(int k, int kt, int waves);
 hipError_t launch_heavy_scan(int64_t n_heavy, const int64_t* rp, const double* w, HeavySet* heavy,
                              hipStream_t st);
 size_t size_order_bytes(int64_t n_sets);

@@ -93,7 +93,7 @@ extern "C" dms_status dms_sketch_csr_noalloc(dms_ctx c, int64_t n_sets, const in
                                          nullptr, ctx_phi0(c), ctx_phi_max(c), cursor,
                                          ctx_resident_blocks(c, kModeMinhash, k, minhash_tile(k)), nullptr, 0,
                                          nullptr, nullptr, 0,
-                                         order, ctx_hash(c), LaunchExtras{}, nullptr, nullptr, st);
+                                         order, ctx_hash(c), LaunchExtras{}, nullptr, nullptr, 0, 0, st);
     }
     if (rc == DMS_OK && e != hipSuccess) rc = ctx_fail(c, DMS_EHIP, hipGetErrorString(e));
     if (prev >= 0 && prev != device) (void)hipSetDevice(prev);

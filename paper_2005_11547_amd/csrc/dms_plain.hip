@@ -45,8 +45,13 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                 const double dnu = ldexp(sp->u, nu - rho);   // column width 2^nu / (t 2^rho)
                 const double drho = ldexp(1.0, rho - nu);    // row height 2^rho / 2^nu
                 // columns w with Wn + w dnu <= x_i, rows r with Rr + r drho <= tau
-                const double n_col = prefix_count(Wn, dnu, xi, ldexp(1.0, rho), floor((xi - Wn) / dnu) + 1.0);
-                const double n_row = prefix_count(Rr, drho, tau, ldexp(1.0, nu), floor((tau - Rr) / drho) + 1.0);
+                // real-number estimates of the counts (1/dnu ~ t 2^(rho-nu), 1/drho = 2^(nu-rho)),
+                // made exact by prefix_count
+                const double td = (double)sp->t;
+                const double n_col = prefix_count(Wn, dnu, xi, ldexp(1.0, rho),
+                                                  floor((xi - Wn) * td * ldexp(1.0, rho - nu)) + 1.0);
+                const double n_row = prefix_count(Rr, drho, tau, ldexp(1.0, nu),
+                                                  floor((tau - Rr) * ldexp(1.0, nu - rho)) + 1.0);
                 if (n_col > 4294967296.0 || n_row > 4294967296.0) { *range = true; break; }
                 const uint64_t g =
                     H(sp->key_r ^ ((id << 32) | ((uint64_t)nu << 16) | (uint64_t)rho));

@@ -236,7 +236,7 @@ dms_status launch_batch(dms_server_s* S, Slot& s, const std::vector<int64_t>& ta
                                                   dms::ctx_phi_max(S->ctx), s.d_counter + g,
                                                   2 * dms::ctx_n_cu(S->ctx), dp, n_parts, dh, db,
                                                   n_parts > 0 ? split : 0, nullptr, dms::ctx_hash(S->ctx),
-                                                  dms::LaunchExtras{}, nullptr, nullptr, st);
+                                                  dms::LaunchExtras{}, nullptr, nullptr, 0, 0, st);
             part_base += n_parts;
             part_heavy += n_heavy;
             bucket_base += n_parts * 2 * (int64_t)k;

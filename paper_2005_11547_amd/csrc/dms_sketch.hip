@@ -1331,6 +1331,22 @@ int minhash_tile(int k)
     const int tiles = (k + kmax - 1) / kmax;
     return ((k + tiles - 1) / tiles + 63) / 64 * 64;
 }
+// The tile for an option value (0: minhash_tile(k); t: t buckets per tile when
+// t < k, a multiple of 64), or 0 when t's minima do not fit one wave's LDS.
+int minhash_tile_for(int k, int t)
+{
+    if (t <= 0 || t >= k) return minhash_tile(k);
+    if (t % 64 || fast_lds(kModeMinhash, k, t, 1) > 65536) return 0;
+    return t;
+}
+// Waves per block for an option value (0: the most resident waves), or 0 when
+// the block does not fit 64 KiB of LDS.
+int minhash_waves_for(int k, int kt, int waves)
+{
+    if (waves <= 0) return fast_waves(kModeMinhash, k, kt);
+    if (waves > 4 || fast_lds(kModeMinhash, k, kt, waves) > 65536) return 0;
+    return waves;
+}
 int fast_waves_per_block(int k) { return fast_waves(kModeMinhash, k, minhash_tile(k)); }
 size_t fast_lds_bytes(int k, int waves) { return fast_lds(kModeMinhash, k, minhash_tile(k), waves); }
 
@@ -1373,12 +1389,14 @@ hipError_t launch_sketch_fast_split(const SpecTables* sp, int64_t n_sets, const 
                                     unsigned long long* counter, int blocks, const void* parts,
                                     int64_t n_parts, void* heavy, uint64_t* partial, int64_t split,
                                     const uint32_t* order, int hash, const LaunchExtras& x,
-                                    const unsigned long long* plan_dev, const uint8_t* planned, hipStream_t st)
+                                    const unsigned long long* plan_dev, const uint8_t* planned, int kt_opt,
+                                    int waves_opt, hipStream_t st)
 {
     if (n_sets <= 0) return hipSuccess;
-    const int kt = minhash_tile(k);
+    const int kt = minhash_tile_for(k, kt_opt);
+    const int waves = minhash_waves_for(k, kt, waves_opt);
+    if (kt <= 0 || waves <= 0) return hipErrorInvalidValue;
     if (kt < k && n_parts > 0) return hipErrorInvalidValue;  // tiled buckets are not split
-    const int waves = fast_waves(kModeMinhash, k, kt);
     const size_t lds = fast_lds(kModeMinhash, k, kt, waves);
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const int64_t need = (n_parts + n_sets + waves - 1) / waves;
@@ -1400,7 +1418,7 @@ hipError_t launch_sketch_fast(const SpecTables* sp, int64_t n_sets, const int64_
 {
     return launch_sketch_fast_split(sp, n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s,
                                     out_rank, phi0, phi_max, counter, blocks, nullptr, 0, nullptr,
-                                    nullptr, 0, nullptr, hash, x, nullptr, nullptr, st);
+                                    nullptr, 0, nullptr, hash, x, nullptr, nullptr, 0, 0, st);
 }
 
 hipError_t launch_lsh_fast(const SpecTables* sp, int64_t n_sets, const int64_t* rp,

@@ -19,6 +19,7 @@ ENGINE_FAST, ENGINE_PLAIN = 0, 1
 OPT_ENGINE, OPT_PHI0, OPT_LSH_PHI0, OPT_PHI_MAX, OPT_SPLIT_NNZ, OPT_BOTTOMK_PHI0, OPT_HASH, OPT_ORDER = (
     0, 1, 2, 3, 4, 5, 6, 7)
 OPT_TIMING = 8
+OPT_WAVES, OPT_TILE = 9, 10
 HASH_MIX, HASH_TAB = 0, 1
 FMT_U32, FMT_1BIT = 0, 1
 FLAG_VALIDATE, FLAG_COUNTERS = 1, 2

@@ -224,7 +224,35 @@ def test_autotune_picks_a_candidate_and_changes_no_output(torch):
     assert phi0 in (1.0, 1.15, 1.3, 1.5, 1.8) and split in (0.0, 1024.0, 4096.0, 16384.0)
     assert c.get_option(dms.OPT_PHI0) == phi0 and c.get_option(dms.OPT_SPLIT_NNZ) == split
     assert c.get_option(dms.OPT_ORDER) in (0.0, 1.0)
+    assert c.get_option(dms.OPT_WAVES) in (0.0, 1.0, 2.0, 3.0, 4.0)
+    assert c.get_option(dms.OPT_TILE) in (0.0, 128.0)
     _check_sketch(torch, c, rp[:401], idx[:rp[400]], w[:rp[400]], 256, f"after autotune phi0={phi0} split={split}")
+    c.close()
+
+
+@pytest.mark.parametrize("k,tile,waves", [(256, 0, 1), (256, 0, 2), (256, 0, 4), (256, 128, 0), (256, 64, 4),
+                                          (1024, 0, 1), (1024, 512, 0), (1024, 512, 2), (1024, 256, 4),
+                                          (64, 0, 3)])
+def test_block_shape_options(torch, k, tile, waves):
+    # waves per block and buckets per tile change the launch, never an output
+    from paper_2005_11547_amd import Context, dms
+    rp, idx, w = WL.uneven_k1024(seed=62, n_sets=300)
+    c = Context(SEED)
+    c.set_option(dms.OPT_TILE, tile)
+    c.set_option(dms.OPT_WAVES, waves)
+    _check_sketch(torch, c, rp, idx, w, k, f"k={k} tile={tile} waves={waves}")
+    c.close()
+
+
+def test_block_shape_that_does_not_fit_is_refused(torch):
+    from paper_2005_11547_amd import Context, dms
+    rp, idx, w = WL.batch_k256(seed=63, n_sets=8)
+    c = Context(SEED)
+    c.set_option(dms.OPT_WAVES, 4)  # four waves of 1024 buckets each exceed 64 KiB
+    with pytest.raises(dms.DMSError):
+        c.sketch(*_dev(torch, rp, idx, w), 1024)
+    with pytest.raises(dms.DMSError):
+        c.set_option(dms.OPT_TILE, 100)  # not a multiple of 64
     c.close()
 
 
