@@ -812,7 +812,7 @@ def main():
     traffic = None
     if args.workload == "batch_k256" and args.engine == "fast":
         from paper_2005_11547_amd import profiling
-        traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", "traffic_sketch_fast_batch_k256.txt"))
+        traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", "traffic_all_benched_kernels.txt"))
     result = {
         "metric": "sketches/sec",
         "value": sets_per_s,

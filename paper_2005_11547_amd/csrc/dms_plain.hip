@@ -24,7 +24,7 @@ struct LaneCounts {
 // first; every area of that grid is hashed and its darts tested against both
 // bounds.  Every accepted dart goes to `sink(rank, s)`.  Sets *range when an
 // index leaves the supported domain.
-template <int HK, class Sink>
+template <int HK, bool CNT, class Sink>
 __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                                               const int32_t* __restrict__ idx,
                                               const double* __restrict__ w, int64_t b0,
@@ -55,7 +55,7 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                 if (n_col > 4294967296.0 || n_row > 4294967296.0) { *range = true; break; }
                 const uint64_t g =
                     H(sp->key_r ^ ((id << 32) | ((uint64_t)nu << 16) | (uint64_t)rho));
-                cnt.reg += 1;
+                if (CNT) cnt.reg += 1;
                 const uint64_t nc = (uint64_t)n_col, nr = (uint64_t)n_row;
                 for (uint64_t wc = 0; wc < nc; ++wc) {
                     const double wd = (double)wc;
@@ -63,17 +63,19 @@ __device__ __forceinline__ void lane_darthash(const SpecTables* __restrict__ sp,
                         const double rd = (double)rc;
                         const uint64_t a = H(g ^ sp->key_a ^ ((wc << 32) | rc));
                         const uint32_t X = poisson_count(sp->pois, a);
-                        cnt.area += 1;
-                        cnt.gen += X;
+                        if (CNT) {
+                            cnt.area += 1;
+                            cnt.gen += X;
+                        }
                         for (uint32_t j = 0; j < X; ++j) {
                             const double U = unit53(H(a ^ sp->key_u ^ (uint64_t)j));
                             const double rank = Rr + (rd + U) * drho;
                             if (!(rank <= tau)) continue;
-                            cnt.rank += 1;
+                            if (CNT) cnt.rank += 1;
                             const double V = unit53(H(a ^ sp->key_v ^ (uint64_t)j));
                             const double weight = Wn + (wd + V) * dnu;
                             if (!(weight <= xi)) continue;
-                            cnt.acc += 1;
+                            if (CNT) cnt.acc += 1;
                             sink(rank, H(a ^ sp->key_s ^ (uint64_t)j));
                         }
                     }
@@ -132,7 +134,7 @@ __device__ __forceinline__ void write_minhash(int64_t set, int k, int lane, int8
 }
 
 // grid: ceil(n_sets / waves) blocks of 64*waves threads; LDS: waves * 16 k bytes.
-template <int HK>
+template <int HK, bool CNT>
 __global__ void __launch_bounds__(256)
 sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                     const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
@@ -168,7 +170,7 @@ sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
             bool range = false;
             passes += 1;
             phi_end = phi;
-            lane_darthash<HK>(sp, idx, w, b0, b1, lane, tau, &range, cnt, [&](double rank, uint64_t s) {
+            lane_darthash<HK, CNT>(sp, idx, w, b0, b1, lane, tau, &range, cnt, [&](double rank, uint64_t s) {
                 bucket_min(rank_bits, sval, bucket_of(s, (uint32_t)k),
                            (uint64_t)__double_as_longlong(rank), s);
             });
@@ -183,7 +185,7 @@ sketch_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
     wave_sync();
     write_minhash(set, k, lane, status, rank_bits, sval, out_u32, out_bits, out_status, out_s,
                   out_rank);
-    if (out_cnt) write_counts(out_cnt, set, lane, cnt, passes, phi_end);
+    if (CNT && out_cnt) write_counts(out_cnt, set, lane, cnt, passes, phi_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,7 +220,7 @@ __device__ __forceinline__ void lsh_insert(const LshLds& T, int K, uint32_t l, u
 }
 
 // LDS per wave: L*K*16 + L*8 bytes.
-template <int HK>
+template <int HK, bool CNT>
 __global__ void __launch_bounds__(256)
 lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
                  const int64_t* __restrict__ rp, const int32_t* __restrict__ idx,
@@ -255,7 +257,7 @@ lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
             bool range = false;
             passes += 1;
             phi_end = phi;
-            lane_darthash<HK>(sp, idx, w, b0, b1, lane, tau, &range, cnt, [&](double rank, uint64_t s) {
+            lane_darthash<HK, CNT>(sp, idx, w, b0, b1, lane, tau, &range, cnt, [&](double rank, uint64_t s) {
                 const uint32_t l = bucket_of(s, (uint32_t)L);
                 const uint64_t rb = (uint64_t)__double_as_longlong(rank);
                 // lanes reaching this point together may target the same table:
@@ -286,7 +288,7 @@ lsh_plain_kernel(const SpecTables* __restrict__ sp, int64_t n_sets,
         out_keys[set * L + l] = h;
     }
     if (out_status && lane == 0) out_status[set] = status;
-    if (out_cnt) write_counts(out_cnt, set, lane, cnt, passes, phi_end);
+    if (CNT && out_cnt) write_counts(out_cnt, set, lane, cnt, passes, phi_end);
 }
 
 }  // namespace dms
@@ -309,7 +311,9 @@ hipError_t launch_sketch_plain(const SpecTables* sp, int64_t n_sets, const int64
     const int waves = plain_waves_per_block(k);
     const int64_t blocks = (n_sets + waves - 1) / waves;
     const size_t lds = (size_t)waves * 16 * k;
-    auto kern = hash == kHashTab ? sketch_plain_kernel<kHashTab> : sketch_plain_kernel<kHashMix>;
+    const bool cnt = x.counters != nullptr;
+    auto kern = hash == kHashTab ? (cnt ? sketch_plain_kernel<kHashTab, true> : sketch_plain_kernel<kHashTab, false>)
+                                 : (cnt ? sketch_plain_kernel<kHashMix, true> : sketch_plain_kernel<kHashMix, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, st, sp,
                        n_sets, rp, idx, w, k, out_u32, out_bits, out_status, out_s, out_rank,
                        phi0, phi_max, x.counters, x.repeated);
@@ -326,7 +330,9 @@ hipError_t launch_lsh_plain(const SpecTables* sp, int64_t n_sets, const int64_t*
     int waves = (int)(65536 / per_wave);
     waves = waves < 1 ? 1 : (waves > 4 ? 4 : waves);
     const int64_t blocks = (n_sets + waves - 1) / waves;
-    auto kern = hash == kHashTab ? lsh_plain_kernel<kHashTab> : lsh_plain_kernel<kHashMix>;
+    const bool cnt = x.counters != nullptr;
+    auto kern = hash == kHashTab ? (cnt ? lsh_plain_kernel<kHashTab, true> : lsh_plain_kernel<kHashTab, false>)
+                                 : (cnt ? lsh_plain_kernel<kHashMix, true> : lsh_plain_kernel<kHashMix, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves),
                        per_wave * waves, st, sp, n_sets, rp, idx, w, L, K, out_keys, out_status,
                        phi0, phi_max, x.counters, x.repeated);
