@@ -94,6 +94,19 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// The first active lane's value as a wave-uniform (scalar) value: the
+// compiler then keeps what depends on it in scalar registers and branches.
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni_f64(double v)
+{
+    return __longlong_as_double((long long)uni64((uint64_t)__double_as_longlong(v)));
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
@@ -150,8 +163,10 @@ __device__ __forceinline__ RowInfo scan_row(const double* __restrict__ w, int64_
         }
     }
     RowInfo ri;
-    ri.sum = wave_sum(sum);
-    mx = wave_max(mx);
+    // every lane holds the same sums and maxima (the butterflies add the same
+    // pairs in every lane); the first lane's are taken as wave-uniform values
+    ri.sum = uni_f64(wave_sum(sum));
+    mx = uni_f64(wave_max(mx));
     if (wave_any(bad)) ri.status = kSetInvalid;
     else if (!(mx > 0.0)) ri.status = kSetEmpty;
     else if (mx > 0x1.0p768 || mx < 0x1.0p-768) ri.status = kSetRange;

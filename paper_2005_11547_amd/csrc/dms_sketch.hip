@@ -104,24 +104,11 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Poisson(1) dart count of an area hash.  C holds the first eight thresholds
-// in registers; `pois` (LDS) the full table for the rare tail.
-__device__ __forceinline__ uint32_t poisson_fast(const uint64_t (&C)[8], const uint64_t* pois,
-                                                 uint64_t a)
-{
-    uint32_t x = (a >= C[0]) + (a >= C[1]) + (a >= C[2]) + (a >= C[3]) + (a >= C[4]) +
-                 (a >= C[5]) + (a >= C[6]) + (a >= C[7]);
-    if (x == 8) {
-        while (x < (uint32_t)kNumPoisson && a >= pois[x]) ++x;
-    }
-    return x;
-}
-
 // min(X, 2) for the Poisson(1) count X of an area hash: enough to tell an
 // empty area, a one-dart area and an area with more darts apart.
-__device__ __forceinline__ uint32_t poisson_head(const uint64_t (&C)[8], uint64_t a)
+__device__ __forceinline__ uint32_t poisson_head(uint64_t C0, uint64_t C1, uint64_t a)
 {
-    return (uint32_t)(a >= C[0]) + (uint32_t)(a >= C[1]);
+    return (uint32_t)(a >= C0) + (uint32_t)(a >= C1);
 }
 
 // LDS of one wave: queues at fixed offsets from the wave's base, then the k
@@ -308,8 +295,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     constexpr bool LSH = MODE == kModeLsh || RT;
     constexpr bool BK = MODE == kModeBottomK;
     // Region and area rounds only need to know whether an area holds no dart,
-    // one, or more (poisson_head); the exact Poisson count is drawn from the
-    // same area hash by the dart round, which sees only areas with two or more.
+    // one, or more (poisson_head); the dart round, which sees only areas with
+    // two or more, tests one further threshold per dart: X > j + 1 iff the
+    // area hash is at least threshold j + 1, so the count itself is never formed.
     extern __shared__ unsigned char smem[];
     double* sW = (double*)smem;
     double* sR = sW + kTable;
@@ -320,9 +308,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     }
     if (threadIdx.x < kNumPoisson) sPois[threadIdx.x] = sp->pois[threadIdx.x];
     __syncthreads();  // the only block barrier
-    uint64_t C[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) C[i] = sPois[i];  // per-lane copies keep scalar registers free
+    // per-lane copies of the first two thresholds keep scalar registers free
+    const uint64_t C0 = sPois[0], C1 = sPois[1];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -702,11 +689,12 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t meta = at<uint32_t>(wb, kOffDqM, rpos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const uint32_t j = (meta >> 20) & 31;
-                        const uint32_t X = poisson_fast(C, sPois, a);
                         const double U = unit53(H(a ^ KU ^ (uint64_t)j));
                         const double rank = r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
                         const bool pass = act && rank <= tau && rank > tau_prev;
-                        const bool more = act && j + 1 < X;
+                        // dart j + 1 exists iff X > j + 1, i.e. the area hash reaches
+                        // threshold j + 1 (X counts the thresholds at or below it)
+                        const bool more = act && j + 1 < (uint32_t)kNumPoisson && a >= sPois[j + 1];
                         const uint64_t bp = __ballot(pass);
                         const uint64_t bm = __ballot(more);
                         if (DBG) {
@@ -781,7 +769,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rv = local - wv * rc;
                             }
                             a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                            X = poisson_head(C, a);
+                            X = poisson_head(C0, C1, a);
                         }
                         if (DBG) n_area += m;
                         emit_area(act, a, ei, rv, wv, meta, X, false);
@@ -811,7 +799,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         if (act) {
                             const uint64_t g = H(KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
                             a = H(g ^ KA);
-                            X = poisson_head(C, a);
+                            X = poisson_head(C0, C1, a);
                         }
                         emit_area(act, a, (uint32_t)(chunk - lo) + (uint32_t)lane, 0u, 0u, low_nu, X, true);
                         low_nu = uni(low_nu + 1);
@@ -857,7 +845,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                     nau = rcu;
                                 }
                                 a = H(g ^ KA);
-                                X = poisson_head(C, a);
+                                X = poisson_head(C0, C1, a);
                                 rest = nau - 1;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, true);
@@ -898,7 +886,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 }
                                 // the region's first area (w = 0, r = 0)
                                 a = H(g ^ KA);
-                                X = poisson_head(C, a);
+                                X = poisson_head(C0, C1, a);
                                 rest = nau - 1;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, false);
@@ -998,7 +986,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     for (;;) {
         unsigned long long got = 0;
         if (lane == 0) got = atomicAdd(next_set, 1ull);
-        const int64_t item = (int64_t)__shfl(got, 0, kWave);
+        const int64_t item = (int64_t)uni64(got);  // lane 0 is the first active lane
         if (item >= np + n_sets) break;
         int64_t set;
         int8_t status;
@@ -1042,7 +1030,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
             __threadfence();  // the buckets are visible before the part counts as done
             int last = 0;
             if (lane == 0) last = atomicAdd(&hs->done, 1) == hs->parts - 1;
-            if (!__shfl(last, 0, kWave)) continue;
+            if (!uni(last)) continue;
             __threadfence();
             if (status == kSetOk && __hip_atomic_load(&hs->range, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 status = kSetRange;
