@@ -54,13 +54,16 @@ __device__ __forceinline__ uint32_t poisson_count(const uint64_t* __restrict__ p
 
 // Lower corners of weight region nu and rank region rho: tables below kTable,
 // exact closed forms above (see corner_w / corner_r in dms_internal.h).
+// (Both sides are evaluated and one is selected: no branch for the lanes.)
 __device__ __forceinline__ double w_corner(const double* tab, double u, int nu)
 {
-    return nu < kTable ? tab[nu] : ldexp(u, nu);
+    const double t = tab[nu < kTable ? nu : kTable - 1];
+    return nu < kTable ? t : ldexp(u, nu);
 }
 __device__ __forceinline__ double r_corner(const double* tab, int rho)
 {
-    return rho < kTable ? tab[rho] : ldexp(1.0, rho);
+    const double t = tab[rho < kTable ? rho : kTable - 1];
+    return rho < kTable ? t : ldexp(1.0, rho);
 }
 
 // Length of the prefix of c in [0, cap) with base + c * step <= bound, for an

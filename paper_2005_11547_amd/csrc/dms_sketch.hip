@@ -62,6 +62,11 @@ __device__ __forceinline__ uint32_t ring(uint32_t p)
     return min(p, p - CAP);
 }
 __device__ __forceinline__ uint32_t ring_r(uint32_t p) { return ring<kCapR>(p); }
+// Ring slot of a position below 2 * cap (a head plus at most 64 entries).
+__device__ __forceinline__ uint32_t ring_r1(uint32_t p)
+{
+    return (kCapR & (kCapR - 1)) == 0 ? p & (kCapR - 1) : min(p, p - kCapR);
+}
 __device__ __forceinline__ uint32_t ring_d(uint32_t p) { return ring<kCapD>(p); }
 __device__ __forceinline__ uint32_t ring_p(uint32_t p) { return ring<kCapP>(p); }
 
@@ -566,13 +571,17 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // as they do for every weight in the supported domain).
                 auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
                                      uint32_t meta, uint32_t X, bool corner) {
+                    // computed on every lane (no branch): lanes without a dart
+                    // are masked out of both tests by `has`
                     const bool has = act && X > 0;
-                    double rank = 0.0;
-                    if (has) {
-                        const int nu = meta & 1023, rho = (meta >> 10) & 1023;
-                        const double U = unit53(H(a ^ KU));
-                        rank = corner ? ldexp(U, -nu)
-                                      : r_corner(sR, rho) + ((double)rv + U) * ldexp(1.0, rho - nu);
+                    const int nu = meta & 1023, rho = (meta >> 10) & 1023;
+                    const uint64_t hu = H(a ^ KU);
+                    double rank;
+                    if (corner) {
+                        // U 2^-nu = (hu >> 11) 2^(-53-nu): one exact scaling
+                        rank = ldexp((double)(hu >> 11), -53 - nu);
+                    } else {
+                        rank = r_corner(sR, rho) + ((double)rv + unit53(hu)) * ldexp(1.0, rho - nu);
                     }
                     const bool pass = has && rank <= tau && rank > tau_prev;
                     const bool more = has && X > 1;
@@ -620,8 +629,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         if (DBG) n_acc += (uint64_t)__popcll(__ballot(acc));
-                        uint64_t s = 0;
-                        if (acc) s = H(a ^ KS ^ j);
+                        const uint64_t s = H(a ^ KS ^ j);  // every lane; used only where acc
                         if (RT) {
                             // a dart above its full table's largest is dropped at once;
                             // the others go to their table's lane through its mailbox,
@@ -727,7 +735,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
                         if ((uint32_t)lane < n_items) {
-                            const uint32_t ip = ring_r(rq_head + lane);
+                            const uint32_t ip = ring_r1(rq_head + lane);
                             na = at<uint32_t>(wb, kOffRqNa, ip);
                             first = at<uint32_t>(wb, kOffRqFirst, ip);
                             c = na - first;
@@ -750,27 +758,23 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t s_first = (uint32_t)__shfl(first, src, kWave);
                         const uint32_t local = s_first + (uint32_t)lane - s_excl;
                         const bool act = (uint32_t)lane < m;
-                        uint32_t X = 0, wv = 0, rv = 0, meta = 0;
-                        uint64_t a = 0;
-                        uint32_t ei = 0;
-                        if (act) {
-                            const uint32_t ip = ring_r(rq_head + (uint32_t)src);
-                            const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
-                            ei = at<uint32_t>(wb, kOffRqE, ip);
+                        // every lane reads an entry of the queue's first 64 (src < 64)
+                        // and hashes; lanes past m are masked out by `act`
+                        const uint32_t ip = ring_r1(rq_head + (uint32_t)src);
+                        const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
+                        const uint32_t ei = at<uint32_t>(wb, kOffRqE, ip);
+                        const uint32_t meta = at<uint32_t>(wb, kOffRqM, ip);
+                        uint32_t wv = 0, rv = local;  // tau < 1: one column, area = row
+                        if (B1 > 1) {
                             const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
-                            const uint32_t nai = at<uint32_t>(wb, kOffRqNa, ip);
-                            meta = at<uint32_t>(wb, kOffRqM, ip);
-                            if (rc == 1) {
-                                wv = local;
-                            } else if (nai == rc) {
-                                rv = local;
-                            } else {
-                                wv = local / rc;
+                            const uint32_t nas = (uint32_t)__shfl(na, src, kWave);
+                            if (act && rc != nas) {
+                                wv = rc == 1 ? local : local / rc;
                                 rv = local - wv * rc;
                             }
-                            a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                            X = poisson_head(C0, C1, a);
                         }
+                        const uint64_t a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
+                        const uint32_t X = poisson_head(C0, C1, a);
                         if (DBG) n_area += m;
                         emit_area(act, a, ei, rv, wv, meta, X, false);
                         // advance the region queue by m areas
@@ -789,18 +793,15 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         // ---------------- low-band round ----------------
                         // region (low_nu, 0) of every lane's element: one area (w = r = 0)
                         const bool act = low_nu < n_low;
-                        uint64_t a = 0;
-                        uint32_t X = 0;
                         if (DBG) {
                             const uint64_t nb = (uint64_t)__popcll(__ballot(act));
                             n_reg += nb;
                             n_area += nb;
                         }
-                        if (act) {
-                            const uint64_t g = H(KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
-                            a = H(g ^ KA);
-                            X = poisson_head(C0, C1, a);
-                        }
+                        // every lane hashes; lanes without a region are masked by `act`
+                        const uint64_t g = H(KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
+                        const uint64_t a = H(g ^ KA);
+                        const uint32_t X = poisson_head(C0, C1, a);
                         emit_area(act, a, (uint32_t)(chunk - lo) + (uint32_t)lane, 0u, 0u, low_nu, X, true);
                         low_nu = uni(low_nu + 1);
                         low_left = wave_any(low_nu < n_low);
@@ -832,21 +833,22 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             // tau < R[1] = 1: every region lies in rank row 0 and has one
                             // column; its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact)
                             const uint32_t nu_base = (uint32_t)__shfl(n_low, src, kWave);
-                            if (act) {
-                                // the element's regions above its low band
-                                const uint32_t nu = nu_base + reg_done + (uint32_t)lane - s_excl;
+                            {
+                                // the element's regions above its low band; every lane
+                                // hashes, lanes past m are masked by `act`
+                                const uint32_t nu = (nu_base + reg_done + (uint32_t)lane - s_excl) & 1023u;
                                 meta = nu;
                                 g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
                                 const double rcn = fmin(floor(ldexp(tau, (int)nu)) + 1.0, ldexp(1.0, (int)nu));
                                 if (rcn >= 2147483648.0) {
-                                    range = true;
+                                    if (act) range = true;
                                 } else {
                                     rcu = (uint32_t)rcn;
                                     nau = rcu;
                                 }
                                 a = H(g ^ KA);
                                 X = poisson_head(C0, C1, a);
-                                rest = nau - 1;
+                                rest = act ? nau - 1 : 0u;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, true);
                         } else {
