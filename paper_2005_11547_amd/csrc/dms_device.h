@@ -132,18 +132,24 @@ __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; 
 
 // Lexicographic (rank, s) minimum of one bucket, shared by the lanes of one
 // wave.  rank is non-negative, so its bit pattern orders like the value.
-// Lanes of the same wave that hit the same bucket in the same instruction are
-// resolved by the three steps; lanes of other waves must not touch the bucket.
+// After the rank minimum, the bucket's rank is read back in the same batch of
+// LDS requests (the wave's LDS operations run in order); the lane whose rank
+// lowered the bucket stores its id hash, then every lane holding the bucket's
+// rank takes the minimum of the id hashes (a lane that met the bucket at an
+// equal rank, from this or an earlier instruction).  Lanes of the same wave
+// that hit the same bucket in the same instruction are resolved by these
+// steps; lanes of other waves must not touch the bucket.
 __device__ __forceinline__ void bucket_min(uint64_t* rank_bits, uint64_t* sval, uint32_t b,
                                            uint64_t rb, uint64_t s)
 {
-    uint64_t old = __hip_atomic_fetch_min(&rank_bits[b], rb, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (rb < old)  // the bucket's rank went down: forget the old id
-        __hip_atomic_store(&sval[b], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    uint64_t cur = __hip_atomic_load(&rank_bits[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (cur == rb)
-        __hip_atomic_fetch_min(&sval[b], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint64_t old = __hip_atomic_fetch_min(&rank_bits[b], rb, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint64_t cur = __hip_atomic_load(&rank_bits[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const bool hold = cur == rb;
+    if (hold && rb < old)  // the bucket's rank went down: the old id hash is void
+        __hip_atomic_store(&sval[b], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    wave_sync();  // the store lands before any minimum of the same bucket
+    if (hold) __hip_atomic_fetch_min(&sval[b], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Validity, positive sum and maximum of one CSR row (lanes over nonzeros).
