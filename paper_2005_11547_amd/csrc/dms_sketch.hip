@@ -354,39 +354,50 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         mb_f[lane] = 0;
         wave_sync();
     }
-    // Inserts (r, v) into this lane's table unless it is already there.  The
-    // position is counted on the rank bits alone; only a lane whose rank equals
-    // an entry's recounts with the id hash (and may find the same dart).
+    // Inserts (r, v) into this lane's sorted table unless it is already there.
+    // Entries ordering below the dart form a prefix, so from the top down each
+    // entry is kept, replaced by the dart, or replaced by the entry below it,
+    // by selects without branches (two comparisons live at a time).  The
+    // order is taken on the rank bits alone; only a lane whose rank equals an
+    // entry's takes the path that also compares id hashes (and may find the
+    // same dart, which then changes nothing).
     auto reg_insert = [&](uint64_t r, uint64_t v) {
-        uint32_t pos = 0;
         bool tie = false;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            pos += tr[m] < r ? 1u : 0u;
-            tie |= tr[m] == r;
-        }
-        bool dup = false;
-        if (tie) {
-            pos = 0;
+        for (int m = 0; m < 8; ++m) tie |= tr[m] == r;
+        if (!tie) {
+            bool below = tr[7] < r;
+#pragma unroll
+            for (int m = 7; m >= 1; --m) {
+                const bool below_prev = tr[m - 1] < r;
+                tr[m] = below ? tr[m] : (below_prev ? r : tr[m - 1]);
+                ts[m] = below ? ts[m] : (below_prev ? v : ts[m - 1]);
+                below = below_prev;
+            }
+            tr[0] = below ? tr[0] : r;
+            ts[0] = below ? ts[0] : v;
+        } else {
+            uint32_t pos = 0;
+            bool dup = false;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 dup |= tr[m] == r && ts[m] == v;
                 pos += (tr[m] < r || (tr[m] == r && ts[m] < v)) ? 1u : 0u;
             }
-        }
-        if (!dup && pos < 8) {
+            if (!dup && pos < 8) {
 #pragma unroll
-            for (int m = 7; m >= 1; --m) {
-                if ((uint32_t)m > pos) {
-                    tr[m] = tr[m - 1];
-                    ts[m] = ts[m - 1];
+                for (int m = 7; m >= 1; --m) {
+                    if ((uint32_t)m > pos) {
+                        tr[m] = tr[m - 1];
+                        ts[m] = ts[m - 1];
+                    }
                 }
-            }
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                if ((uint32_t)m == pos) {
-                    tr[m] = r;
-                    ts[m] = v;
+                for (int m = 0; m < 8; ++m) {
+                    if ((uint32_t)m == pos) {
+                        tr[m] = r;
+                        ts[m] = v;
+                    }
                 }
             }
         }
