@@ -666,8 +666,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                         pending = false;
                                     }
                                     wave_sync();
-                                    if (mb_f[lane]) {
-                                        const uint64_t r2 = mb_r[lane], v2 = mb_s[lane];
+                                    // flag and dart are read together (one LDS round trip)
+                                    const uint32_t got = mb_f[lane];
+                                    const uint64_t r2 = mb_r[lane], v2 = mb_s[lane];
+                                    if (got) {
                                         mb_f[lane] = 0;
                                         reg_insert(r2, v2);
                                     }
