@@ -405,6 +405,15 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
 
     const uint64_t KR = sp->key_r, KA = sp->key_a, KU = sp->key_u, KV = sp->key_v, KS = sp->key_s;
     const Hasher<HK> H(sp);
+    // Hash of z for the lanes that use it (`live`).  The mixer runs on every
+    // lane without a branch (masked-out lanes cost no extra instructions);
+    // table lookups are issued only by the lanes that need them.
+    auto HL = [&](bool live, uint64_t z) -> uint64_t {
+        if (HK == kHashMix) return H(z);
+        uint64_t h = 0;
+        if (live) h = H(z);
+        return h;
+    };
     const double u = sp->u;
     const double td = (double)sp->t;
 
@@ -582,11 +591,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // as they do for every weight in the supported domain).
                 auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
                                      uint32_t meta, uint32_t X, bool corner) {
-                    // computed on every lane (no branch): lanes without a dart
-                    // are masked out of both tests by `has`
+                    // lanes without a dart are masked out of both tests by `has`
                     const bool has = act && X > 0;
                     const int nu = meta & 1023, rho = (meta >> 10) & 1023;
-                    const uint64_t hu = H(a ^ KU);
+                    const uint64_t hu = HL(has, a ^ KU);
                     double rank;
                     if (corner) {
                         // U 2^-nu = (hu >> 11) 2^(-53-nu): one exact scaling
@@ -640,7 +648,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         if (DBG) n_acc += (uint64_t)__popcll(__ballot(acc));
-                        const uint64_t s = H(a ^ KS ^ j);  // every lane; used only where acc
+                        const uint64_t s = HL(acc, a ^ KS ^ j);  // used only where acc
                         if (RT) {
                             // a dart above its full table's largest is dropped at once;
                             // the others go to their table's lane through its mailbox,
@@ -771,8 +779,8 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint32_t s_first = (uint32_t)__shfl(first, src, kWave);
                         const uint32_t local = s_first + (uint32_t)lane - s_excl;
                         const bool act = (uint32_t)lane < m;
-                        // every lane reads an entry of the queue's first 64 (src < 64)
-                        // and hashes; lanes past m are masked out by `act`
+                        // every lane reads an entry of the queue's first 64 (src < 64);
+                        // lanes past m are masked out by `act`
                         const uint32_t ip = ring_r1(rq_head + (uint32_t)src);
                         const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
                         const uint32_t ei = at<uint32_t>(wb, kOffRqE, ip);
@@ -786,7 +794,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rv = local - wv * rc;
                             }
                         }
-                        const uint64_t a = H(g ^ KA ^ (((uint64_t)wv << 32) | rv));
+                        const uint64_t a = HL(act, g ^ KA ^ (((uint64_t)wv << 32) | rv));
                         const uint32_t X = poisson_head(C0, C1, a);
                         if (DBG) n_area += m;
                         emit_area(act, a, ei, rv, wv, meta, X, false);
@@ -811,9 +819,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             n_reg += nb;
                             n_area += nb;
                         }
-                        // every lane hashes; lanes without a region are masked by `act`
-                        const uint64_t g = H(KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
-                        const uint64_t a = H(g ^ KA);
+                        // lanes without a region are masked by `act`
+                        const uint64_t g = HL(act, KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
+                        const uint64_t a = HL(act, g ^ KA);
                         const uint32_t X = poisson_head(C0, C1, a);
                         emit_area(act, a, (uint32_t)(chunk - lo) + (uint32_t)lane, 0u, 0u, low_nu, X, true);
                         low_nu = uni(low_nu + 1);
@@ -847,11 +855,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             // column; its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact)
                             const uint32_t nu_base = (uint32_t)__shfl(n_low, src, kWave);
                             {
-                                // the element's regions above its low band; every lane
-                                // hashes, lanes past m are masked by `act`
+                                // the element's regions above its low band; lanes past
+                                // m are masked by `act`
                                 const uint32_t nu = (nu_base + reg_done + (uint32_t)lane - s_excl) & 1023u;
                                 meta = nu;
-                                g = H(KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
+                                g = HL(act, KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
                                 const double rcn = fmin(floor(ldexp(tau, (int)nu)) + 1.0, ldexp(1.0, (int)nu));
                                 if (rcn >= 2147483648.0) {
                                     if (act) range = true;
@@ -859,7 +867,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                     rcu = (uint32_t)rcn;
                                     nau = rcu;
                                 }
-                                a = H(g ^ KA);
+                                a = HL(act, g ^ KA);
                                 X = poisson_head(C0, C1, a);
                                 rest = act ? nau - 1 : 0u;
                             }
