@@ -589,36 +589,44 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // r = 0): its rank R[0] + (0 + U) 2^-nu is U 2^-nu exactly (R[0] = 0,
                 // and scaling by a power of two is exact while ranks stay normal,
                 // as they do for every weight in the supported domain).
-                auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
-                                     uint32_t meta, uint32_t X, bool corner) {
-                    // lanes without a dart are masked out of both tests by `has`
-                    const bool has = act && X > 0;
-                    const int nu = meta & 1023, rho = (meta >> 10) & 1023;
-                    const uint64_t hu = HL(has, a ^ KU);
+                struct FirstDart {
                     double rank;
+                    bool has, pass, more;
+                };
+                auto first_dart = [&](bool act, uint64_t a, uint32_t rv, uint32_t meta, uint32_t X,
+                                      bool corner) -> FirstDart {
+                    // lanes without a dart are masked out of both tests by `has`
+                    FirstDart f;
+                    f.has = act && X > 0;
+                    const int nu = meta & 1023, rho = (meta >> 10) & 1023;
+                    const uint64_t hu = HL(f.has, a ^ KU);
                     if (corner) {
                         // U 2^-nu = (hu >> 11) 2^(-53-nu): one exact scaling
-                        rank = ldexp((double)(hu >> 11), -53 - nu);
+                        f.rank = ldexp((double)(hu >> 11), -53 - nu);
                     } else {
-                        rank = r_corner(sR, rho) + ((double)rv + unit53(hu)) * ldexp(1.0, rho - nu);
+                        f.rank = r_corner(sR, rho) + ((double)rv + unit53(hu)) * ldexp(1.0, rho - nu);
                     }
-                    const bool pass = has && rank <= tau && rank > tau_prev;
-                    const bool more = has && X > 1;
-                    const uint64_t bp = __ballot(pass);
-                    const uint64_t bm = __ballot(more);
+                    f.pass = f.has && f.rank <= tau && f.rank > tau_prev;
+                    f.more = f.has && X > 1;
+                    return f;
+                };
+                auto push_area = [&](const FirstDart& f, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
+                                     uint32_t meta) {
+                    const uint64_t bp = __ballot(f.pass);
+                    const uint64_t bm = __ballot(f.more);
                     if (DBG) {
-                        n_gen += (uint64_t)__popcll(__ballot(has));
+                        n_gen += (uint64_t)__popcll(__ballot(f.has));
                         n_rank += (uint64_t)__popcll(bp);
                     }
-                    if (pass) {
+                    if (f.pass) {
                         const uint32_t pos = ring_p(pq_head + pq_count + rank_in(bp));
                         at<uint64_t>(wb, kOffPqA, pos) = a;
                         at<uint32_t>(wb, kOffPqE, pos) = ei;
-                        at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(rank);
+                        at<uint64_t>(wb, kOffPqRank, pos) = (uint64_t)__double_as_longlong(f.rank);
                         at<uint32_t>(wb, kOffPqW, pos) = wv;
                         at<uint32_t>(wb, kOffPqM, pos) = meta;
                     }
-                    if (more) {
+                    if (f.more) {
                         const uint32_t pos = ring_d(dq_head + dq_count + rank_in(bm));
                         at<uint64_t>(wb, kOffDqA, pos) = a;
                         at<uint32_t>(wb, kOffDqE, pos) = ei;
@@ -628,6 +636,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     }
                     pq_count = uni(pq_count + (uint32_t)__popcll(bp));
                     dq_count = uni(dq_count + (uint32_t)__popcll(bm));
+                };
+                auto emit_area = [&](bool act, uint64_t a, uint32_t ei, uint32_t rv, uint32_t wv,
+                                     uint32_t meta, uint32_t X, bool corner) {
+                    push_area(first_dart(act, a, rv, meta, X, corner), a, ei, rv, wv, meta);
                 };
 
                 for (;;) {
@@ -812,8 +824,14 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         }
                     } else if (have_chunk && low_left) {
                         // ---------------- low-band round ----------------
-                        // region (low_nu, 0) of every lane's element: one area (w = r = 0)
+                        // regions (low_nu, 0) and, while some lane has it, (low_nu + 1, 0) of
+                        // every lane's element: one area each (w = r = 0).  The two levels are
+                        // independent hash chains; the second is kept only if both queues
+                        // still have room for its darts, else it is made again next round.
+                        const uint32_t e_lane = (uint32_t)(chunk - lo) + (uint32_t)lane;
                         const bool act = low_nu < n_low;
+                        const bool act2 = low_nu + 1 < n_low;
+                        const bool two = wave_any(act2);
                         if (DBG) {
                             const uint64_t nb = (uint64_t)__popcll(__ballot(act));
                             n_reg += nb;
@@ -823,7 +841,27 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint64_t g = HL(act, KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
                         const uint64_t a = HL(act, g ^ KA);
                         const uint32_t X = poisson_head(C0, C1, a);
-                        emit_area(act, a, (uint32_t)(chunk - lo) + (uint32_t)lane, 0u, 0u, low_nu, X, true);
+                        const FirstDart f = first_dart(act, a, 0u, low_nu, X, true);
+                        if (two) {
+                            const uint64_t g2 = HL(act2, KR ^ (((uint64_t)eid << 32) | ((uint64_t)(low_nu + 1) << 16)));
+                            const uint64_t a2 = HL(act2, g2 ^ KA);
+                            const uint32_t X2 = poisson_head(C0, C1, a2);
+                            const FirstDart f2 = first_dart(act2, a2, 0u, low_nu + 1, X2, true);
+                            push_area(f, a, e_lane, 0u, 0u, low_nu);
+                            const uint32_t np2 = (uint32_t)__popcll(__ballot(f2.pass));
+                            const uint32_t nm2 = (uint32_t)__popcll(__ballot(f2.more));
+                            if (pq_count + np2 <= kCapP && dq_count + nm2 <= kCapD) {
+                                if (DBG) {
+                                    const uint64_t nb = (uint64_t)__popcll(__ballot(act2));
+                                    n_reg += nb;
+                                    n_area += nb;
+                                }
+                                push_area(f2, a2, e_lane, 0u, 0u, low_nu + 1);
+                                low_nu = uni(low_nu + 1);
+                            }
+                        } else {
+                            push_area(f, a, e_lane, 0u, 0u, low_nu);
+                        }
                         low_nu = uni(low_nu + 1);
                         low_left = wave_any(low_nu < n_low);
                         if (!low_left && chunk_total == 0) {
