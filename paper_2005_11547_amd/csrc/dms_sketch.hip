@@ -52,6 +52,8 @@ constexpr uint32_t kCapD = DMS_CAP_D;  // dart queue (areas with darts left)
 constexpr uint32_t kCapP = DMS_CAP_P;  // pass queue (darts with rank <= tau)
 static_assert(kCapR >= 64 && kCapD >= 64 && kCapP >= 64, "a round moves up to 64 entries");
 constexpr uint32_t kTrigR = kCapR - 64, kTrigD = kCapD - 64, kTrigP = kCapP - 64;
+// Low-band levels made per round (independent hash chains between LDS round trips).
+constexpr int kLowLevels = 3;
 
 // Ring slot of a position below 3 * cap (a head below cap plus two counts).
 template <uint32_t CAP>
@@ -824,45 +826,55 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         }
                     } else if (have_chunk && low_left) {
                         // ---------------- low-band round ----------------
-                        // regions (low_nu, 0) and, while some lane has it, (low_nu + 1, 0) of
-                        // every lane's element: one area each (w = r = 0).  The two levels are
-                        // independent hash chains; the second is kept only if both queues
-                        // still have room for its darts, else it is made again next round.
+                        // regions (low_nu + i, 0), i < n (n <= kLowLevels: the levels some lane
+                        // still has), of every lane's element: one area each (w = r = 0),
+                        // made as independent hash chains.  Level i > 0 is kept only while
+                        // both queues still have room for its darts; otherwise it is made
+                        // again next round.
                         const uint32_t e_lane = (uint32_t)(chunk - lo) + (uint32_t)lane;
-                        const bool act = low_nu < n_low;
-                        const bool act2 = low_nu + 1 < n_low;
-                        const bool two = wave_any(act2);
-                        if (DBG) {
-                            const uint64_t nb = (uint64_t)__popcll(__ballot(act));
-                            n_reg += nb;
-                            n_area += nb;
-                        }
-                        // lanes without a region are masked by `act`
-                        const uint64_t g = HL(act, KR ^ (((uint64_t)eid << 32) | ((uint64_t)low_nu << 16)));
-                        const uint64_t a = HL(act, g ^ KA);
-                        const uint32_t X = poisson_head(C0, C1, a);
-                        const FirstDart f = first_dart(act, a, 0u, low_nu, X, true);
-                        if (two) {
-                            const uint64_t g2 = HL(act2, KR ^ (((uint64_t)eid << 32) | ((uint64_t)(low_nu + 1) << 16)));
-                            const uint64_t a2 = HL(act2, g2 ^ KA);
-                            const uint32_t X2 = poisson_head(C0, C1, a2);
-                            const FirstDart f2 = first_dart(act2, a2, 0u, low_nu + 1, X2, true);
-                            push_area(f, a, e_lane, 0u, 0u, low_nu);
-                            const uint32_t np2 = (uint32_t)__popcll(__ballot(f2.pass));
-                            const uint32_t nm2 = (uint32_t)__popcll(__ballot(f2.more));
-                            if (pq_count + np2 <= kCapP && dq_count + nm2 <= kCapD) {
-                                if (DBG) {
-                                    const uint64_t nb = (uint64_t)__popcll(__ballot(act2));
-                                    n_reg += nb;
-                                    n_area += nb;
-                                }
-                                push_area(f2, a2, e_lane, 0u, 0u, low_nu + 1);
-                                low_nu = uni(low_nu + 1);
+                        auto low_levels = [&](auto levels) {
+                            constexpr int N = decltype(levels)::value;
+                            bool actl[N];
+                            uint64_t gl[N], al[N];
+                            FirstDart fl[N];
+                            // stage by stage across the levels, so the chains interleave
+#pragma unroll
+                            for (int i = 0; i < N; ++i) {
+                                // lanes without a region are masked by `act`
+                                actl[i] = low_nu + (uint32_t)i < n_low;
+                                gl[i] = HL(actl[i], KR ^ (((uint64_t)eid << 32) | ((uint64_t)(low_nu + i) << 16)));
                             }
-                        } else {
-                            push_area(f, a, e_lane, 0u, 0u, low_nu);
-                        }
-                        low_nu = uni(low_nu + 1);
+#pragma unroll
+                            for (int i = 0; i < N; ++i) al[i] = HL(actl[i], gl[i] ^ KA);
+#pragma unroll
+                            for (int i = 0; i < N; ++i)
+                                fl[i] = first_dart(actl[i], al[i], 0u, low_nu + i, poisson_head(C0, C1, al[i]), true);
+                            bool go = true;
+#pragma unroll
+                            for (int i = 0; i < N; ++i) {
+                                if (i > 0) {
+                                    const uint32_t np = (uint32_t)__popcll(__ballot(fl[i].pass));
+                                    const uint32_t nm = (uint32_t)__popcll(__ballot(fl[i].more));
+                                    go = go && pq_count + np <= kCapP && dq_count + nm <= kCapD;
+                                }
+                                if (go) {
+                                    if (DBG) {
+                                        const uint64_t nb = (uint64_t)__popcll(__ballot(actl[i]));
+                                        n_reg += nb;
+                                        n_area += nb;
+                                    }
+                                    push_area(fl[i], al[i], e_lane, 0u, 0u, low_nu);
+                                    low_nu = uni(low_nu + 1);
+                                }
+                            }
+                        };
+                        static_assert(kLowLevels == 3, "the dispatch below makes one to three levels");
+                        if (wave_any(low_nu + 2 < n_low))
+                            low_levels(std::integral_constant<int, 3>{});
+                        else if (wave_any(low_nu + 1 < n_low))
+                            low_levels(std::integral_constant<int, 2>{});
+                        else
+                            low_levels(std::integral_constant<int, 1>{});
                         low_left = wave_any(low_nu < n_low);
                         if (!low_left && chunk_total == 0) {
                             chunk += kWave;
