@@ -767,6 +767,10 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         dq_count = uni(dq_left + (uint32_t)__popcll(bm));
                     } else if (rq_count > kTrigR || (rq_count > 0 && !have_chunk)) {
                         // ---------------- area round ----------------
+                        // the queue's next areas, up to 64 per half: two halves (two
+                        // independent hash chains per lane) while more than 64 areas wait.
+                        // The second half is kept only while both queues still have room
+                        // for its darts; otherwise its areas are made again next round.
                         const uint32_t n_items = rq_count < 64 ? rq_count : 64;
                         uint32_t na = 0, first = 0, c = 0;
                         if ((uint32_t)lane < n_items) {
@@ -775,55 +779,103 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             first = at<uint32_t>(wb, kOffRqFirst, ip);
                             c = na - first;
                         }
-                        const uint32_t cc = c < 64 ? c : 64;
+                        const uint32_t cc = c < 128 ? c : 128;
                         const uint32_t incl = scan_add(cc);
                         const uint32_t excl = incl - cc;
                         const uint32_t total = uni(lane63(incl));
-                        const uint32_t m = total < 64 ? total : 64;
-                        if (m == 0) {  // bookkeeping guard: never spin without progress
+                        if (total == 0) {  // bookkeeping guard: never spin without progress
                             range = true;
                             break;
                         }
-                        at<int32_t>(wb, kOffMark, lane) = 0;
-                        wave_sync();
-                        if (cc > 0 && excl < 64) at<int32_t>(wb, kOffMark, excl) = lane;
-                        wave_sync();
-                        const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
-                        const uint32_t s_excl = (uint32_t)__shfl(excl, src, kWave);
-                        const uint32_t s_first = (uint32_t)__shfl(first, src, kWave);
-                        const uint32_t local = s_first + (uint32_t)lane - s_excl;
-                        const bool act = (uint32_t)lane < m;
-                        // every lane reads an entry of the queue's first 64 (src < 64);
-                        // lanes past m are masked out by `act`
-                        const uint32_t ip = ring_r1(rq_head + (uint32_t)src);
-                        const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
-                        const uint32_t ei = at<uint32_t>(wb, kOffRqE, ip);
-                        const uint32_t meta = at<uint32_t>(wb, kOffRqM, ip);
-                        uint32_t wv = 0, rv = local;  // tau < 1: one column, area = row
-                        if (B1 > 1) {
-                            const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
-                            const uint32_t nas = (uint32_t)__shfl(na, src, kWave);
-                            if (act && rc != nas) {
-                                wv = rc == 1 ? local : local / rc;
-                                rv = local - wv * rc;
+                        auto area_halves = [&](auto halves) {
+                            constexpr int NH = decltype(halves)::value;
+                            const uint32_t m = total < 64u * NH ? total : 64u * NH;
+                            int32_t src[NH];
+                            uint32_t local[NH];
+                            int32_t carry = 0;  // entry holding the first area of the half
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) {
+                                // entry of each area: the last entry whose areas start at or
+                                // before it (marks at the starts, then a prefix maximum)
+                                at<int32_t>(wb, kOffMark, lane) = 0;
+                                wave_sync();
+                                if (cc > 0 && excl >= 64u * h && excl < 64u * (h + 1))
+                                    at<int32_t>(wb, kOffMark, excl - 64u * h) = lane;
+                                wave_sync();
+                                int32_t v = at<int32_t>(wb, kOffMark, lane);
+                                if (lane == 0) v = max(v, carry);
+                                src[h] = scan_max(v);
+                                carry = __builtin_amdgcn_readlane(src[h], 63);
+                                const uint32_t s_excl = (uint32_t)__shfl(excl, src[h], kWave);
+                                const uint32_t s_first = (uint32_t)__shfl(first, src[h], kWave);
+                                local[h] = s_first + (64u * h + (uint32_t)lane) - s_excl;
                             }
-                        }
-                        const uint64_t a = HL(act, g ^ KA ^ (((uint64_t)wv << 32) | rv));
-                        const uint32_t X = poisson_head(C0, C1, a);
-                        if (DBG) n_area += m;
-                        emit_area(act, a, ei, rv, wv, meta, X, false);
-                        // advance the region queue by m areas
-                        const uint32_t last_src = (uint32_t)__builtin_amdgcn_readlane(src, (int)m - 1);
-                        const uint32_t last_local = (uint32_t)__builtin_amdgcn_readlane((int)local, (int)m - 1);
-                        const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
-                        if (last_local + 1 == last_na) {
-                            rq_head = uni(ring_r(rq_head + last_src + 1));
-                            rq_count = uni(rq_count - (last_src + 1));
-                        } else {
-                            if (lane == 0) at<uint32_t>(wb, kOffRqFirst, ring_r(rq_head + last_src)) = last_local + 1;
-                            rq_head = uni(ring_r(rq_head + last_src));
-                            rq_count = uni(rq_count - last_src);
-                        }
+                            bool actv[NH];
+                            uint32_t eiv[NH], metav[NH], wvv[NH], rvv[NH];
+                            uint64_t av[NH];
+                            FirstDart fv[NH];
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) {
+                                actv[h] = 64u * h + (uint32_t)lane < m;
+                                // every lane reads an entry of the queue's first 64 (src < 64);
+                                // lanes past m are masked out by `act`
+                                const uint32_t ip = ring_r1(rq_head + (uint32_t)src[h]);
+                                const uint64_t g = at<uint64_t>(wb, kOffRqG, ip);
+                                eiv[h] = at<uint32_t>(wb, kOffRqE, ip);
+                                metav[h] = at<uint32_t>(wb, kOffRqM, ip);
+                                wvv[h] = 0;
+                                rvv[h] = local[h];  // tau < 1: one column, area = row
+                                if (B1 > 1) {
+                                    const uint32_t rc = at<uint32_t>(wb, kOffRqRc, ip);
+                                    const uint32_t nas = (uint32_t)__shfl(na, src[h], kWave);
+                                    if (actv[h] && rc != nas) {
+                                        wvv[h] = rc == 1 ? local[h] : local[h] / rc;
+                                        rvv[h] = local[h] - wvv[h] * rc;
+                                    }
+                                }
+                                av[h] = HL(actv[h], g ^ KA ^ (((uint64_t)wvv[h] << 32) | rvv[h]));
+                            }
+#pragma unroll
+                            for (int h = 0; h < NH; ++h)
+                                fv[h] = first_dart(actv[h], av[h], rvv[h], metav[h], poisson_head(C0, C1, av[h]), false);
+                            uint32_t done = 0;  // areas made this round
+                            bool go = true;
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) {
+                                if (h > 0) {
+                                    const uint32_t np = (uint32_t)__popcll(__ballot(fv[h].pass));
+                                    const uint32_t nm = (uint32_t)__popcll(__ballot(fv[h].more));
+                                    go = go && pq_count + np <= kCapP && dq_count + nm <= kCapD;
+                                }
+                                if (go) {
+                                    push_area(fv[h], av[h], eiv[h], rvv[h], wvv[h], metav[h]);
+                                    done = m < 64u * (h + 1) ? m : 64u * (h + 1);
+                                }
+                            }
+                            if (DBG) n_area += done;
+                            // advance the region queue by `done` areas
+                            const int pl = (int)((done - 1) & 63u);
+                            int32_t s_last = __builtin_amdgcn_readlane(src[0], pl);
+                            uint32_t l_last = (uint32_t)__builtin_amdgcn_readlane((int)local[0], pl);
+                            if (NH > 1 && done > 64) {
+                                s_last = __builtin_amdgcn_readlane(src[NH - 1], pl);
+                                l_last = (uint32_t)__builtin_amdgcn_readlane((int)local[NH - 1], pl);
+                            }
+                            const uint32_t last_src = (uint32_t)s_last;
+                            const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
+                            if (l_last + 1 == last_na) {
+                                rq_head = uni(ring_r(rq_head + last_src + 1));
+                                rq_count = uni(rq_count - (last_src + 1));
+                            } else {
+                                if (lane == 0) at<uint32_t>(wb, kOffRqFirst, ring_r(rq_head + last_src)) = l_last + 1;
+                                rq_head = uni(ring_r(rq_head + last_src));
+                                rq_count = uni(rq_count - last_src);
+                            }
+                        };
+                        if (total > 64)
+                            area_halves(std::integral_constant<int, 2>{});
+                        else
+                            area_halves(std::integral_constant<int, 1>{});
                     } else if (have_chunk && low_left) {
                         // ---------------- low-band round ----------------
                         // regions (low_nu + i, 0), i < n (n <= kLowLevels: the levels some lane
