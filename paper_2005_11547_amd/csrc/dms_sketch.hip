@@ -854,12 +854,16 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                             }
                             if (DBG) n_area += done;
                             // advance the region queue by `done` areas
-                            const int pl = (int)((done - 1) & 63u);
+                            const int pl = (int)((done - 1) & 63u);  // last area: lane pl of half hl
+                            const uint32_t hl = (done - 1) >> 6;
                             int32_t s_last = __builtin_amdgcn_readlane(src[0], pl);
                             uint32_t l_last = (uint32_t)__builtin_amdgcn_readlane((int)local[0], pl);
-                            if (NH > 1 && done > 64) {
-                                s_last = __builtin_amdgcn_readlane(src[NH - 1], pl);
-                                l_last = (uint32_t)__builtin_amdgcn_readlane((int)local[NH - 1], pl);
+#pragma unroll
+                            for (int h = 1; h < NH; ++h) {
+                                if (hl == (uint32_t)h) {
+                                    s_last = __builtin_amdgcn_readlane(src[h], pl);
+                                    l_last = (uint32_t)__builtin_amdgcn_readlane((int)local[h], pl);
+                                }
                             }
                             const uint32_t last_src = (uint32_t)s_last;
                             const uint32_t last_na = (uint32_t)__builtin_amdgcn_readlane((int)na, (int)last_src);
