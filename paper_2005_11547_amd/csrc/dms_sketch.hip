@@ -939,46 +939,111 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                     } else if (have_chunk) {
                         // ---------------- region round ----------------
                         const uint32_t left = chunk_total - reg_done;
-                        const uint32_t m = left < 64 ? left : 64;
-                        if (DBG) {
-                            n_reg += m;
-                            n_area += m;  // every region's first area (w = r = 0)
-                        }
-                        at<int32_t>(wb, kOffMark, lane) = 0;
-                        wave_sync();
-                        if (nreg > 0 && nreg_excl + nreg > reg_done && nreg_excl < reg_done + 64)
-                            at<int32_t>(wb, kOffMark, nreg_excl > reg_done ? nreg_excl - reg_done : 0) = lane;
-                        wave_sync();
-                        const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
-                        const uint32_t id = (uint32_t)__shfl(eid, src, kWave);
-                        const uint32_t s_excl = (uint32_t)__shfl(nreg_excl, src, kWave);
-                        const bool act = (uint32_t)lane < m;
-                        const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
-                        uint32_t X = 0, rest = 0, meta = 0, rcu = 1, nau = 1;
-                        uint64_t a = 0, g = 0;
-                        if (B1 == 1) {
-                            // tau < R[1] = 1: every region lies in rank row 0 and has one
-                            // column; its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact)
-                            const uint32_t nu_base = (uint32_t)__shfl(n_low, src, kWave);
-                            {
-                                // the element's regions above its low band; lanes past
-                                // m are masked by `act`
-                                const uint32_t nu = (nu_base + reg_done + (uint32_t)lane - s_excl) & 1023u;
-                                meta = nu;
-                                g = HL(act, KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
+                        // tau < R[1] = 1: every region lies in rank row 0 and has one column;
+                        // its rows are r <= tau 2^nu (R[0] = 0, r 2^-nu exact).  Up to 128
+                        // regions as two halves of independent hash chains while more than
+                        // 64 are left; the second half is kept only while the three queues
+                        // have room for what it adds, else it is made again next round.
+                        auto region_halves = [&](auto halves) {
+                            constexpr int NH = decltype(halves)::value;
+                            const uint32_t m = left < 64u * NH ? left : 64u * NH;
+                            bool actv[NH];
+                            uint32_t ev[NH], metav[NH], rcv[NH], restv[NH];
+                            uint64_t gv[NH], av[NH];
+                            FirstDart fv[NH];
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) {
+                                // element of each region: marks where an element's regions
+                                // start in the window (at 0 for one started before it)
+                                const uint32_t base = reg_done + 64u * h;
+                                at<int32_t>(wb, kOffMark, lane) = 0;
+                                wave_sync();
+                                if (nreg > 0 && nreg_excl + nreg > base && nreg_excl < base + 64)
+                                    at<int32_t>(wb, kOffMark, nreg_excl > base ? nreg_excl - base : 0) = lane;
+                                wave_sync();
+                                const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
+                                const uint32_t id = (uint32_t)__shfl(eid, src, kWave);
+                                const uint32_t s_excl = (uint32_t)__shfl(nreg_excl, src, kWave);
+                                const uint32_t nu_base = (uint32_t)__shfl(n_low, src, kWave);
+                                actv[h] = 64u * h + (uint32_t)lane < m;
+                                ev[h] = (uint32_t)(chunk - lo) + (uint32_t)src;
+                                // the element's regions above its low band; lanes past m are
+                                // masked by `act`
+                                const uint32_t nu = (nu_base + base + (uint32_t)lane - s_excl) & 1023u;
+                                metav[h] = nu;
+                                gv[h] = HL(actv[h], KR ^ (((uint64_t)id << 32) | ((uint64_t)nu << 16)));
                                 const double rcn = fmin(floor(ldexp(tau, (int)nu)) + 1.0, ldexp(1.0, (int)nu));
+                                rcv[h] = 1;
                                 if (rcn >= 2147483648.0) {
-                                    if (act) range = true;
+                                    if (actv[h]) range = true;
                                 } else {
-                                    rcu = (uint32_t)rcn;
-                                    nau = rcu;
+                                    rcv[h] = (uint32_t)rcn;
                                 }
-                                a = HL(act, g ^ KA);
-                                X = poisson_head(C0, C1, a);
-                                rest = act ? nau - 1 : 0u;
+                                restv[h] = actv[h] ? rcv[h] - 1 : 0u;
                             }
-                            emit_area(act, a, e, 0u, 0u, meta, X, true);
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) av[h] = HL(actv[h], gv[h] ^ KA);
+#pragma unroll
+                            for (int h = 0; h < NH; ++h)
+                                fv[h] = first_dart(actv[h], av[h], 0u, metav[h], poisson_head(C0, C1, av[h]), true);
+                            uint32_t done = 0;
+                            bool go = true;
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) {
+                                const bool push_r = restv[h] > 0;
+                                const uint64_t br = __ballot(push_r);
+                                if (h > 0) {
+                                    const uint32_t np = (uint32_t)__popcll(__ballot(fv[h].pass));
+                                    const uint32_t nm = (uint32_t)__popcll(__ballot(fv[h].more));
+                                    go = go && pq_count + np <= kCapP && dq_count + nm <= kCapD &&
+                                         rq_count + (uint32_t)__popcll(br) <= kCapR;
+                                }
+                                if (go) {
+                                    push_area(fv[h], av[h], ev[h], 0u, 0u, metav[h]);
+                                    if (push_r) {
+                                        const uint32_t pos = ring_r(rq_head + rq_count + rank_in(br));
+                                        at<uint64_t>(wb, kOffRqG, pos) = gv[h];
+                                        at<uint32_t>(wb, kOffRqE, pos) = ev[h];
+                                        at<uint32_t>(wb, kOffRqRc, pos) = rcv[h];
+                                        at<uint32_t>(wb, kOffRqNa, pos) = rcv[h];
+                                        at<uint32_t>(wb, kOffRqFirst, pos) = 1;
+                                        at<uint32_t>(wb, kOffRqM, pos) = metav[h];
+                                    }
+                                    rq_count = uni(rq_count + (uint32_t)__popcll(br));
+                                    done = m < 64u * (h + 1) ? m : 64u * (h + 1);
+                                }
+                            }
+                            if (DBG) {
+                                n_reg += done;
+                                n_area += done;  // every region's first area (w = r = 0)
+                            }
+                            reg_done = uni(reg_done + done);
+                        };
+                        if (B1 == 1) {
+                            // (two halves pay off where region rounds dominate, as for
+                            // bottom-k with no low band; measured slower for the others)
+                            if (BK && left > 64)
+                                region_halves(std::integral_constant<int, 2>{});
+                            else
+                                region_halves(std::integral_constant<int, 1>{});
                         } else {
+                            const uint32_t m = left < 64 ? left : 64;
+                            if (DBG) {
+                                n_reg += m;
+                                n_area += m;  // every region's first area (w = r = 0)
+                            }
+                            at<int32_t>(wb, kOffMark, lane) = 0;
+                            wave_sync();
+                            if (nreg > 0 && nreg_excl + nreg > reg_done && nreg_excl < reg_done + 64)
+                                at<int32_t>(wb, kOffMark, nreg_excl > reg_done ? nreg_excl - reg_done : 0) = lane;
+                            wave_sync();
+                            const int32_t src = scan_max(at<int32_t>(wb, kOffMark, lane));
+                            const uint32_t id = (uint32_t)__shfl(eid, src, kWave);
+                            const uint32_t s_excl = (uint32_t)__shfl(nreg_excl, src, kWave);
+                            const bool act = (uint32_t)lane < m;
+                            const uint32_t e = (uint32_t)(chunk - lo) + (uint32_t)src;
+                            uint32_t X = 0, rest = 0, meta = 0, rcu = 1, nau = 1;
+                            uint64_t a = 0, g = 0;
                             const double x = __shfl(ex, src, kWave);
                             if (act) {
                                 // region `local` of the element: nu = local / B1, rho = local % B1
@@ -1019,20 +1084,20 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 rest = nau - 1;
                             }
                             emit_area(act, a, e, 0u, 0u, meta, X, false);
+                            const bool push_r = act && rest > 0;
+                            const uint64_t br = __ballot(push_r);
+                            if (push_r) {
+                                const uint32_t pos = ring_r(rq_head + rq_count + rank_in(br));
+                                at<uint64_t>(wb, kOffRqG, pos) = g;
+                                at<uint32_t>(wb, kOffRqE, pos) = e;
+                                at<uint32_t>(wb, kOffRqRc, pos) = rcu;
+                                at<uint32_t>(wb, kOffRqNa, pos) = nau;
+                                at<uint32_t>(wb, kOffRqFirst, pos) = 1;
+                                at<uint32_t>(wb, kOffRqM, pos) = meta;
+                            }
+                            rq_count = uni(rq_count + (uint32_t)__popcll(br));
+                            reg_done = uni(reg_done + m);
                         }
-                        const bool push_r = act && rest > 0;
-                        const uint64_t br = __ballot(push_r);
-                        if (push_r) {
-                            const uint32_t pos = ring_r(rq_head + rq_count + rank_in(br));
-                            at<uint64_t>(wb, kOffRqG, pos) = g;
-                            at<uint32_t>(wb, kOffRqE, pos) = e;
-                            at<uint32_t>(wb, kOffRqRc, pos) = rcu;
-                            at<uint32_t>(wb, kOffRqNa, pos) = nau;
-                            at<uint32_t>(wb, kOffRqFirst, pos) = 1;
-                            at<uint32_t>(wb, kOffRqM, pos) = meta;
-                        }
-                        rq_count = uni(rq_count + (uint32_t)__popcll(br));
-                        reg_done = uni(reg_done + m);
                         if (wave_any(range)) break;
                         if (reg_done == chunk_total) {
                             chunk += kWave;
