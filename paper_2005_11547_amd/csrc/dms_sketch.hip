@@ -658,11 +658,14 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         const uint64_t rb = at<uint64_t>(wb, kOffPqRank, pos);
                         const int nu = meta & 1023, rho = (meta >> 10) & 1023;
                         const uint64_t j = (meta >> 20) & 31;
+                        // the id hash does not depend on the weight test: with the mixer
+                        // it is drawn first, so both hash chains cover the wait for x_i
+                        uint64_t s = HK == kHashMix ? H(a ^ KS ^ j) : 0ull;  // used only where acc
                         const double V = unit53(H(a ^ KV ^ j));
                         const double weight = w_corner(sW, u, nu) + ((double)wv + V) * ldexp(u, nu - rho);
                         const bool acc = (uint32_t)lane < m && weight <= xi;
                         if (DBG) n_acc += (uint64_t)__popcll(__ballot(acc));
-                        const uint64_t s = HL(acc, a ^ KS ^ j);  // used only where acc
+                        if (HK != kHashMix) s = HL(acc, a ^ KS ^ j);
                         if (RT) {
                             // a dart above its full table's largest is dropped at once;
                             // the others go to their table's lane through its mailbox,
