@@ -2,9 +2,13 @@
 //
 // One wavefront sketches one set at a time, pulling set indices from a global
 // counter until the batch is exhausted (persistent grid, work stealing).  The
-// five nested loops of Algorithm 1 are flattened into four kinds of rounds
+// five nested loops of Algorithm 1 are flattened into five kinds of rounds
 // that run 64 lanes wide, connected by small queues in LDS:
 //
+//   low-band round : in a pass with tau < 1, the regions of an element below
+//                  nu = -ilogb(tau) hold one area each; one lane per element
+//                  hashes such a region, its area and its first dart's rank,
+//                  up to three levels nu per round as independent hash chains.
 //   region round : expands elements into their (nu, rho) regions, hashes the
 //                  region (g) and its first area (a), tells from a whether the
 //                  area holds no dart, one, or more, and draws its first
@@ -12,13 +16,19 @@
 //                  passing darts to the pass queue, areas with more darts to
 //                  the dart queue.
 //   area round   : expands queued regions into their remaining areas, hashes
-//                  them and draws their first ranks (as above).
+//                  them and draws their first ranks (as above), up to 128 areas
+//                  per round as two halves of independent hash chains.
 //   dart round   : draws the rank uniform of the next dart of each queued
-//                  area (and the area's exact Poisson(1) count); darts with
-//                  rank <= tau go to the pass queue; an area with more darts
-//                  goes back to the dart queue.
+//                  area; darts with rank <= tau go to the pass queue; an area
+//                  with more darts (one more Poisson threshold reached) goes
+//                  back to the dart queue.
 //   accept round : draws the weight uniform; darts with weight <= x_i get their
-//                  id hash and enter the bucket minima.
+//                  id hash and enter the sink (bucket minima, LSH tables or the
+//                  bottom-k buffer).
+//
+// Every decision about which round runs is wave-uniform, and the compiler
+// sees it (scalar branches and registers); inside a round, lanes without work
+// are masked by their flags rather than branched around.
 //
 // Column and row counts of a region come from a closed form corrected with the
 // exact loop-exit predicate (prefix_count), so the visited areas are exactly
@@ -33,7 +43,8 @@ namespace {
 // Every queue is a ring.  A round consumes up to 64 entries and pushes at most
 // 64 into each queue it feeds, and it runs only while every queue it feeds
 // holds at most cap - 64 entries (its consumer takes priority above that), so
-// no ring overflows.  The region ring is the smaller one: its rounds are the
+// no ring overflows; a round that makes a second level or half pushes it only
+// after checking that the queues still have room for it.  The region ring is the smaller one: its rounds are the
 // costliest, and region entries come from few rounds; the dart and pass rings
 // hold two rounds so that their (cheaper) consumers always run 64 lanes wide.
 // With these sizes three waves of k = 256 fit 40,960 bytes, so twelve waves

@@ -23,11 +23,24 @@ KERNEL_SOURCES = ["csrc/dms_sketch.hip", "csrc/dms_device.h", "csrc/dms_internal
 COPY_KERNEL = "calib_copy_kernel"
 
 
+def code_text(text: str) -> str:
+    """The code of a C++/HIP source without // comments, blank lines and
+    indentation (the kernel sources hold no block comments and no string
+    literal with two slashes), so that comment edits keep a profile valid."""
+    lines = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].strip()
+        if code:
+            lines.append(code)
+    return "\n".join(lines)
+
+
 def source_hash() -> str:
+    """Hash of the code of the sketch kernel's sources (comments excluded)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
