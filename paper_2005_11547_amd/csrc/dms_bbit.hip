@@ -33,7 +33,7 @@ bbit_pack_vec_kernel(int64_t n_vecs, const uint4* __restrict__ v, int b, int g_l
     const int G = 1 << g_log;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of 64: groups stay whole
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_vecs; q += stride) {
-        const uint4 x = v[q];
+        const uint4 x = load_stream(v + q);
         if (b == 32) {
             reinterpret_cast<uint4*>(out)[q] = x;  // two words: minhash 2i low, 2i + 1 high
             continue;
@@ -58,7 +58,7 @@ unary_map_vec_kernel(int64_t n_vecs, const uint4* __restrict__ v, int k, int b, 
     uint32_t j = (uint32_t)((4 * q) % k);
     const uint32_t step = (uint32_t)((4 * stride) % k);
     for (; q < n_vecs; q += stride) {
-        const uint4 x = v[q];
+        const uint4 x = load_stream(v + q);
         uint4 y;
         y.x = (j << b) + (x.x & mask);
         y.y = ((j + 1) << b) + (x.y & mask);

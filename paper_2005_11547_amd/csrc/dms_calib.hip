@@ -57,8 +57,9 @@ __global__ void __launch_bounds__(256) calib_copy_kernel(const uint4* __restrict
 }
 
 // The same copy with four 16-byte loads in flight per thread before its four
-// stores (each of the four coalesced across the block), and stores that
-// bypass the caches on the way to HBM; the tail is copied one vector at a time.
+// stores (each of the four coalesced across the block), loads and stores both
+// marked non-temporal (streamed past the caches); the tail is copied one vector
+// at a time.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) calib_copy4_kernel(const u32x4* __restrict__ src,
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(256) calib_copy4_kernel(const u32x4* __restric
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; base < full; base += step) {
         u32x4 v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = src[base + j * blockDim.x];
+        for (int j = 0; j < 4; ++j) v[j] = __builtin_nontemporal_load(&src[base + j * blockDim.x]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(v[j], &dst[base + j * blockDim.x]);
     }

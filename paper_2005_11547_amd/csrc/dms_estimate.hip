@@ -72,7 +72,7 @@ pair_vec_kernel(int64_t n_pairs, const uint4* __restrict__ a, const uint4* __res
         uint32_t c = 0;
 #pragma unroll 4
         for (int v = r; v < vecs; v += G) {
-            const uint4 x = a[p * vecs + v], y = b[p * vecs + v];
+            const uint4 x = load_stream(a + p * vecs + v), y = load_stream(b + p * vecs + v);
             if (FMT == 0) {
                 c += (x.x == y.x) + (x.y == y.y) + (x.z == y.z) + (x.w == y.w);
             } else {
