@@ -437,7 +437,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     uint64_t cut_r = ~0ull, cut_s = ~0ull;
     // Sort the buffer by (rank, id hash), drop repeated darts and keep at most
     // the k smallest (the k-th becomes the cutoff).  All 64 lanes call it.
-    auto bk_compact = [&]() {
+    // Up to 512 darts are sorted in registers (below); larger buffers by a
+    // bitonic network over LDS.
+    auto bk_compact_lds = [&]() __attribute__((always_inline)) {
         const uint32_t n = bk_count;
         uint32_t N = 64;
         while (N < n) N <<= 1;
@@ -501,6 +503,122 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
         }
         bk_count = D;
         wave_sync();
+    };
+    // The same for n <= 64 NR darts held in registers: element e = 64 i + lane
+    // sits in slot i of its lane, entries past n are empty (all ones).  The
+    // bitonic network is the form without directions: each merge of two
+    // sorted runs of size/2 first compares e with its mirror e ^ (size - 1),
+    // then halves with every pair in ascending order, so an empty entry never
+    // moves and a step whose upper element lies in a slot past n is skipped.
+    // Exchanges between lanes go through lane permutes, those between slots
+    // stay in the lane: no LDS round trip per step.  The repeats are then
+    // dropped on the sorted registers and the distinct darts written to the
+    // front of the buffer.
+    auto bk_compact_reg = [&](auto slots) __attribute__((always_inline)) {
+        constexpr int NR = decltype(slots)::value;
+        const uint32_t n = bk_count;
+        uint64_t R[NR], V[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const uint32_t e = 64u * i + (uint32_t)lane;
+            R[i] = ~0ull;
+            V[i] = ~0ull;
+            if (e < n) {
+                R[i] = bin_rank[e];
+                V[i] = bin_s[e];
+            }
+        }
+        // one step between lanes of each occupied slot: partner lane ^ mask;
+        // the lane for which `lower` holds keeps the smaller entry
+        auto lane_step = [&](int mask, bool lower) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                if (64u * i >= n) continue;
+                const uint64_t pr = __shfl_xor(R[i], mask, kWave);
+                const uint64_t pv = __shfl_xor(V[i], mask, kWave);
+                const bool own_less = R[i] < pr || (R[i] == pr && V[i] < pv);
+                const bool take = lower ? !own_less : own_less;
+                R[i] = take ? pr : R[i];
+                V[i] = take ? pv : V[i];
+            }
+        };
+        // one step between slots i (lower) and i ^ MS of the same lane (flip = false,
+        // MS a power of two) or of lane ^ 63 (the mirror step of a merge of size > 64)
+        auto slot_step = [&](auto msc, auto flipc) __attribute__((always_inline)) {
+            constexpr int MS = decltype(msc)::value;
+            constexpr bool flip = decltype(flipc)::value;
+            constexpr int HB = flip ? (MS + 1) >> 1 : MS;  // the slot bit that tells lower from upper
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int j = i ^ MS;
+                if ((i & HB) != 0 || j >= NR) continue;
+                if (64u * j >= n) continue;  // the upper slot is empty
+                uint64_t ar = R[j], av = V[j], br = R[i], bv = V[i];
+                if constexpr (flip) {
+                    ar = __shfl_xor(ar, 63, kWave);
+                    av = __shfl_xor(av, 63, kWave);
+                    br = __shfl_xor(br, 63, kWave);
+                    bv = __shfl_xor(bv, 63, kWave);
+                }
+                const bool i_less = R[i] < ar || (R[i] == ar && V[i] < av);
+                const bool j_less = R[j] < br || (R[j] == br && V[j] < bv);
+                R[i] = i_less ? R[i] : ar;
+                V[i] = i_less ? V[i] : av;
+                R[j] = j_less ? br : R[j];
+                V[j] = j_less ? bv : V[j];
+            }
+        };
+        for (uint32_t size = 2; size <= 64u * NR; size <<= 1) {
+            if (size <= 64u) lane_step((int)size - 1, ((uint32_t)lane & (size >> 1)) == 0);
+            else if (size == 128u) slot_step(std::integral_constant<int, 1>{}, std::true_type{});
+            else if (size == 256u) slot_step(std::integral_constant<int, 3>{}, std::true_type{});
+            else slot_step(std::integral_constant<int, 7>{}, std::true_type{});
+            for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+                if (stride < 64u) lane_step((int)stride, ((uint32_t)lane & stride) == 0);
+                else if (stride == 64u) slot_step(std::integral_constant<int, 1>{}, std::false_type{});
+                else if (stride == 128u) slot_step(std::integral_constant<int, 2>{}, std::false_type{});
+                else slot_step(std::integral_constant<int, 4>{}, std::false_type{});
+            }
+        }
+        wave_sync();  // every entry is read before the front is rewritten
+        uint32_t D = 0;
+        uint64_t last_r = 0, last_v = 0;  // element 64 i - 1 (lane 63 of slot i - 1)
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (64u * i >= n) continue;  // empty slots come last
+            const uint32_t e = 64u * i + (uint32_t)lane;
+            const int from = lane == 0 ? 0 : lane - 1;
+            uint64_t pr = __shfl(R[i], from, kWave), pv = __shfl(V[i], from, kWave);
+            if (lane == 0) {
+                pr = last_r;
+                pv = last_v;
+            }
+            const bool keep = e < n && (e == 0 || R[i] != pr || V[i] != pv);
+            const uint64_t bm = __ballot(keep);
+            if (keep) {
+                const uint32_t q = D + rank_in(bm);
+                bin_rank[q] = R[i];
+                bin_s[q] = V[i];
+            }
+            D = uni(D + (uint32_t)__popcll(bm));
+            last_r = uni64(__shfl(R[i], 63, kWave));
+            last_v = uni64(__shfl(V[i], 63, kWave));
+        }
+        wave_sync();
+        if (D > (uint32_t)k) {
+            D = (uint32_t)k;
+            cut_r = bin_rank[k - 1];
+            cut_s = bin_s[k - 1];
+        }
+        bk_count = D;
+        wave_sync();
+    };
+    auto bk_compact = [&]() __attribute__((always_inline)) {
+        if (bk_count <= 64u) bk_compact_reg(std::integral_constant<int, 1>{});
+        else if (bk_count <= 128u) bk_compact_reg(std::integral_constant<int, 2>{});
+        else if (bk_count <= 256u) bk_compact_reg(std::integral_constant<int, 4>{});
+        else if (bk_count <= 512u) bk_compact_reg(std::integral_constant<int, 8>{});
+        else bk_compact_lds();
     };
 
     // Enumeration counts of the current set or part (wave-uniform): regions,
