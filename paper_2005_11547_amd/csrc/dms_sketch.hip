@@ -528,58 +528,84 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 V[i] = bin_s[e];
             }
         }
-        // one step between lanes of each occupied slot: partner lane ^ mask;
-        // the lane for which `lower` holds keeps the smaller entry
-        auto lane_step = [&](int mask, bool lower) __attribute__((always_inline)) {
+        // The network orders by the rank bits alone (FULL = false) or by (rank,
+        // id hash).  Distinct darts of equal rank are rare: the rank order is
+        // taken when no two neighbours share a rank, else the network runs
+        // again on the full order (repeated darts always take that path).
+        auto sort_slots = [&](auto fullc) __attribute__((always_inline)) {
+            constexpr bool FULL = decltype(fullc)::value;
+            auto less = [&](uint64_t ar, uint64_t av, uint64_t br, uint64_t bv) {
+                return FULL ? ar < br || (ar == br && av < bv) : ar < br;
+            };
+            // one step between lanes of each occupied slot: partner lane ^ mask;
+            // the lane for which `lower` holds keeps the smaller entry
+            auto lane_step = [&](int mask, bool lower) __attribute__((always_inline)) {
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    if (64u * i >= n) continue;
+                    const uint64_t pr = __shfl_xor(R[i], mask, kWave);
+                    const uint64_t pv = __shfl_xor(V[i], mask, kWave);
+                    const bool own_less = less(R[i], V[i], pr, pv);
+                    const bool take = lower ? !own_less : own_less;
+                    R[i] = take ? pr : R[i];
+                    V[i] = take ? pv : V[i];
+                }
+            };
+            // one step between slots i (lower) and i ^ MS of the same lane (flip =
+            // false, MS a power of two) or of lane ^ 63 (the mirror step of a merge
+            // of size > 64)
+            auto slot_step = [&](auto msc, auto flipc) __attribute__((always_inline)) {
+                constexpr int MS = decltype(msc)::value;
+                constexpr bool flip = decltype(flipc)::value;
+                constexpr int HB = flip ? (MS + 1) >> 1 : MS;  // the slot bit that tells lower from upper
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const int j = i ^ MS;
+                    if ((i & HB) != 0 || j >= NR) continue;
+                    if (64u * j >= n) continue;  // the upper slot is empty
+                    uint64_t ar = R[j], av = V[j], br = R[i], bv = V[i];
+                    if constexpr (flip) {
+                        ar = __shfl_xor(ar, 63, kWave);
+                        av = __shfl_xor(av, 63, kWave);
+                        br = __shfl_xor(br, 63, kWave);
+                        bv = __shfl_xor(bv, 63, kWave);
+                    }
+                    const bool i_less = less(R[i], V[i], ar, av);
+                    const bool j_less = less(R[j], V[j], br, bv);
+                    R[i] = i_less ? R[i] : ar;
+                    V[i] = i_less ? V[i] : av;
+                    R[j] = j_less ? br : R[j];
+                    V[j] = j_less ? bv : V[j];
+                }
+            };
+            for (uint32_t size = 2; size <= 64u * NR; size <<= 1) {
+                if (size <= 64u) lane_step((int)size - 1, ((uint32_t)lane & (size >> 1)) == 0);
+                else if (size == 128u) slot_step(std::integral_constant<int, 1>{}, std::true_type{});
+                else if (size == 256u) slot_step(std::integral_constant<int, 3>{}, std::true_type{});
+                else slot_step(std::integral_constant<int, 7>{}, std::true_type{});
+                for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+                    if (stride < 64u) lane_step((int)stride, ((uint32_t)lane & stride) == 0);
+                    else if (stride == 64u) slot_step(std::integral_constant<int, 1>{}, std::false_type{});
+                    else if (stride == 128u) slot_step(std::integral_constant<int, 2>{}, std::false_type{});
+                    else slot_step(std::integral_constant<int, 4>{}, std::false_type{});
+                }
+            }
+        };
+        sort_slots(std::false_type{});
+        bool tie = false;  // some entry has its predecessor's rank
+        {
+            uint64_t last = ~0ull;  // rank of element 64 i - 1
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 if (64u * i >= n) continue;
-                const uint64_t pr = __shfl_xor(R[i], mask, kWave);
-                const uint64_t pv = __shfl_xor(V[i], mask, kWave);
-                const bool own_less = R[i] < pr || (R[i] == pr && V[i] < pv);
-                const bool take = lower ? !own_less : own_less;
-                R[i] = take ? pr : R[i];
-                V[i] = take ? pv : V[i];
-            }
-        };
-        // one step between slots i (lower) and i ^ MS of the same lane (flip = false,
-        // MS a power of two) or of lane ^ 63 (the mirror step of a merge of size > 64)
-        auto slot_step = [&](auto msc, auto flipc) __attribute__((always_inline)) {
-            constexpr int MS = decltype(msc)::value;
-            constexpr bool flip = decltype(flipc)::value;
-            constexpr int HB = flip ? (MS + 1) >> 1 : MS;  // the slot bit that tells lower from upper
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const int j = i ^ MS;
-                if ((i & HB) != 0 || j >= NR) continue;
-                if (64u * j >= n) continue;  // the upper slot is empty
-                uint64_t ar = R[j], av = V[j], br = R[i], bv = V[i];
-                if constexpr (flip) {
-                    ar = __shfl_xor(ar, 63, kWave);
-                    av = __shfl_xor(av, 63, kWave);
-                    br = __shfl_xor(br, 63, kWave);
-                    bv = __shfl_xor(bv, 63, kWave);
-                }
-                const bool i_less = R[i] < ar || (R[i] == ar && V[i] < av);
-                const bool j_less = R[j] < br || (R[j] == br && V[j] < bv);
-                R[i] = i_less ? R[i] : ar;
-                V[i] = i_less ? V[i] : av;
-                R[j] = j_less ? br : R[j];
-                V[j] = j_less ? bv : V[j];
-            }
-        };
-        for (uint32_t size = 2; size <= 64u * NR; size <<= 1) {
-            if (size <= 64u) lane_step((int)size - 1, ((uint32_t)lane & (size >> 1)) == 0);
-            else if (size == 128u) slot_step(std::integral_constant<int, 1>{}, std::true_type{});
-            else if (size == 256u) slot_step(std::integral_constant<int, 3>{}, std::true_type{});
-            else slot_step(std::integral_constant<int, 7>{}, std::true_type{});
-            for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
-                if (stride < 64u) lane_step((int)stride, ((uint32_t)lane & stride) == 0);
-                else if (stride == 64u) slot_step(std::integral_constant<int, 1>{}, std::false_type{});
-                else if (stride == 128u) slot_step(std::integral_constant<int, 2>{}, std::false_type{});
-                else slot_step(std::integral_constant<int, 4>{}, std::false_type{});
+                const uint32_t e = 64u * i + (uint32_t)lane;
+                uint64_t pr = __shfl(R[i], lane == 0 ? 0 : lane - 1, kWave);
+                if (lane == 0) pr = last;
+                tie = tie || (e < n && e > 0 && R[i] == pr);
+                last = uni64(__shfl(R[i], 63, kWave));
             }
         }
+        if (wave_any(tie)) sort_slots(std::true_type{});
         wave_sync();  // every entry is read before the front is rewritten
         uint32_t D = 0;
         uint64_t last_r = 0, last_v = 0;  // element 64 i - 1 (lane 63 of slot i - 1)
