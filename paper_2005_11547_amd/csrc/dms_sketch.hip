@@ -676,8 +676,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                 // regions below nu_split (tau 2^nu < 1, i.e. nu < -ilogb(tau)) are a
                 // single area each: the "low band", walked by lockstep rounds over
                 // nu with one element per lane and no expansion.
-                // (Measured: the bottom-k sink runs faster without it.)
-                const int nu_split = !BK && B1 == 1 ? max(0, -ilogb(tau)) : 0;
+                const int nu_split = B1 == 1 ? max(0, -ilogb(tau)) : 0;
 
                 const int64_t b1 = hi;
                 int64_t chunk = lo;        // first element of the current chunk
@@ -1179,7 +1178,7 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         };
                         if (B1 == 1) {
                             // (two halves pay off where region rounds dominate, as for
-                            // bottom-k with no low band; measured slower for the others)
+                            // bottom-k; measured slower for the others)
                             if (BK && left > 64)
                                 region_halves(std::integral_constant<int, 2>{});
                             else
