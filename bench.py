@@ -357,7 +357,7 @@ def secondary_runs(ctx, torch, steps=3, main=None, c_mix=None):
                                                             counters=True)["counters"][:, 0]
                 fold = 64 * (8 + 1)  # the key of each table folds its K ids, one mixer each, plus its seed
             else:
-                r = O.bottomk_csr(s_rp, s_idx, s_w, 256, WL.HASH_SEED, phi0=1.0 + 4.0 / 16.0,
+                r = O.bottomk_csr(s_rp, s_idx, s_w, 256, WL.HASH_SEED, phi0=1.0 + 3.0 / 16.0,
                                   schedule=O.SCHED_DOUBLE, counters=True)
                 rc, paper = r["counters"][:, 0], O.bottomk_csr(s_rp, s_idx, s_w, 256, WL.HASH_SEED,
                                                                 counters=True)["counters"][:, 0]

@@ -68,7 +68,7 @@ typedef int32_t dms_status;
                                scratch of fixed capacity (twice the batch's sets, at least 1024
                                parts, at most 256 MiB of partial buckets); a heavy set that no
                                longer fits is sketched whole by one wave (same outputs). */
-#define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 4/sqrt(k)) */
+#define DMS_OPT_BOTTOMK_PHI0 5 /* first phi of the bottom-k schedule (default 0: 1 + 3/sqrt(k)) */
 #define DMS_OPT_HASH 6      /* DMS_HASH_*: the hash of every hashing step (default DMS_HASH_MIX).
                                Unlike the other options it changes the outputs: sketches made
                                with different hashes are not comparable. */

@@ -42,7 +42,7 @@ struct dms_ctx_s {
     // than the larger first pass saves (Theorem 1's retry argument)
     double phi0 = 1.3;
     double lsh_phi0 = 2.5;  // (64,8) LSH: fastest of 2, 2.5, 3, 3.5, 4 on 1M sets
-    double bottomk_phi0 = 0.0;  // 0: 1 + 4/sqrt(k)
+    double bottomk_phi0 = 0.0;  // 0: 1 + 3/sqrt(k)
     int hash = dms::kHashMix;   // DMS_HASH_*
     int order = 1;              // DMS_OPT_ORDER: largest sets first
     int waves = 0;              // DMS_OPT_WAVES: waves per block of the minhash kernel (0: automatic)
@@ -481,8 +481,9 @@ dms_status dms_bottomk(dms_ctx c, int64_t n_sets, const int64_t* row_ptr, const 
     if (st != DMS_OK) return st;
     dms::LaunchExtras x;
     if ((st = prepare_extras(c, n_sets, row_ptr, idx, flags, out_counters, &x)) != DMS_OK) return st;
-    // phi0 = 1 + 4/sqrt(k) finds k darts in the first pass but for a 4-sigma shortfall
-    const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 4.0 / std::sqrt((double)k);
+    // phi0 = 1 + 3/sqrt(k) finds k darts in the first pass but for a shortfall of about
+    // 3 standard deviations (measured fastest at k = 256: 1.15-1.2 against 1.25 and 1.3)
+    const double phi0 = c->bottomk_phi0 > 0.0 ? c->bottomk_phi0 : 1.0 + 3.0 / std::sqrt((double)k);
     const uint32_t* order = nullptr;
     if (dms_status so = size_order(c, n_sets, row_ptr, &order); so != DMS_OK) return so;
     KernelTimer tm(c);
