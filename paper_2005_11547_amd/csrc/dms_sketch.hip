@@ -174,17 +174,14 @@ __host__ __device__ constexpr size_t lsh_aux_bytes(int L)
     return (size_t)((L + 7) / 8) * 8 + (L > 64 ? (size_t)4 * L : 0);
 }
 
-// Register-table LSH: a mailbox per table (rank bits, id hash, full flag)
-// through which a dart reaches the lane that holds its table.
-constexpr uint32_t kMailboxBytes = 64 * (8 + 8 + 4);
-
 // Bytes of the result area after the queues: the minima of K buckets (minhash:
 // K is the tile of buckets a wave holds at once, k when untiled), L sorted
-// lists of K darts plus their bookkeeping (LSH), a mailbox per table
-// (register-table LSH), or the dart buffer (bottom-k).
+// lists of K darts plus their bookkeeping (LSH), nothing (register-table LSH:
+// the tables are in registers, their mailboxes in the pass queue's slots that
+// the accept round has just read), or the dart buffer (bottom-k).
 __host__ __device__ constexpr size_t sink_bytes(int mode, int k, int K)
 {
-    return mode == kModeLshReg ? (size_t)kMailboxBytes
+    return mode == kModeLshReg ? (size_t)0
          : mode == kModeLsh ? (size_t)16 * k * K + lsh_aux_bytes(k)
          : mode == kModeBottomK ? (size_t)16 * bk_cap(k)
                                 : (size_t)16 * K;
@@ -351,21 +348,15 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     // Register tables: lane l holds table l (l < L), its darts sorted by (rank
     // bits, id hash) in tr/ts; unused entries hold rank bits ~0, above every
     // rank (ranks are finite), so the table is full once tr[7] != ~0.  A dart
-    // reaches its table's lane through the table's mailbox (mb_r, mb_s, and
-    // mb_f = 1 while it holds a dart).
+    // reaches its table's lane through the table's mailbox: during an accept
+    // round, the pass-queue slot pq_head + l, whose entry the round has read,
+    // holds table l's rank bits, id hash and a flag (1 while it holds a dart).
     constexpr uint64_t kNoRank = ~0ull;
     uint64_t tr[8], ts[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         tr[m] = kNoRank;
         ts[m] = 0;
-    }
-    uint64_t* const mb_r = reinterpret_cast<uint64_t*>(wb + kOffBins);
-    uint64_t* const mb_s = mb_r + 64;
-    uint32_t* const mb_f = reinterpret_cast<uint32_t*>(mb_s + 64);
-    if (RT) {
-        mb_f[lane] = 0;
-        wave_sync();
     }
     // Inserts (r, v) into this lane's sorted table unless it is already there.
     // Entries ordering below the dart form a prefix, so from the top down each
@@ -832,6 +823,11 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                 int32_t* const ticket = &at<int32_t>(wb, kOffMark, 0);
                                 if (pending)
                                     __hip_atomic_store(&ticket[l], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                // the mailboxes: the 64 slots from pq_head, all read above
+                                // (a round of m < 64 darts takes the whole queue)
+                                const uint32_t mb_in = ring_p(pq_head + (uint32_t)lane);
+                                const uint32_t mb_out = ring_p(pq_head + l);
+                                at<uint32_t>(wb, kOffPqM, mb_in) = 0;
                                 wave_sync();
                                 int mine = 0;
                                 if (pending)
@@ -839,17 +835,18 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                                 for (int level = 0; wave_any(pending); ++level) {
                                     if (pending && mine == level) {
-                                        mb_r[l] = rb;
-                                        mb_s[l] = s;
-                                        mb_f[l] = 1;
+                                        at<uint64_t>(wb, kOffPqA, mb_out) = rb;
+                                        at<uint64_t>(wb, kOffPqRank, mb_out) = s;
+                                        at<uint32_t>(wb, kOffPqM, mb_out) = 1;
                                         pending = false;
                                     }
                                     wave_sync();
                                     // flag and dart are read together (one LDS round trip)
-                                    const uint32_t got = mb_f[lane];
-                                    const uint64_t r2 = mb_r[lane], v2 = mb_s[lane];
+                                    const uint32_t got = at<uint32_t>(wb, kOffPqM, mb_in);
+                                    const uint64_t r2 = at<uint64_t>(wb, kOffPqA, mb_in);
+                                    const uint64_t v2 = at<uint64_t>(wb, kOffPqRank, mb_in);
                                     if (got) {
-                                        mb_f[lane] = 0;
+                                        at<uint32_t>(wb, kOffPqM, mb_in) = 0;
                                         reg_insert(r2, v2);
                                     }
                                     wave_sync();
