@@ -155,11 +155,15 @@ constexpr uint32_t kOffBins = kOffMark + 4 * 64;             // u64[k] rank bits
 constexpr uint32_t kQueueBytes = kOffBins;
 constexpr uint32_t kTablesBytes = 16 * kTable + 8 * kNumPoisson;  // W, R, Poisson thresholds
 
-// Dart buffer of a bottom-k wave: a power of two of at least 2k entries with
-// at least k + 64 of them, so that after a compaction (at most k entries kept)
-// a whole round of accepted darts always fits.
+// Dart buffer of a bottom-k wave: at least k + 64 entries, so that after a
+// compaction (at most k entries kept) a whole round of accepted darts always
+// fits.  Up to k = 384 it is k + 128 rounded up to whole 64-entry slots (at most
+// 512: always sorted in registers; at k = 256 it holds a first pass's darts
+// with room to spare, and 10 waves fit a CU instead of 9 with 512 entries);
+// beyond, a power of two of at least 2k entries for the bitonic network over LDS.
 __host__ __device__ constexpr uint32_t bk_cap(int k)
 {
+    if (k <= 384) return (uint32_t)(k + 128 + 63) / 64 * 64;
     uint32_t need = (uint32_t)(2 * k > k + 64 ? 2 * k : k + 64), c = 64;
     while (c < need) c <<= 1;
     return c;
