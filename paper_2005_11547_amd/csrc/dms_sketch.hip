@@ -432,8 +432,9 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
     uint64_t cut_r = ~0ull, cut_s = ~0ull;
     // Sort the buffer by (rank, id hash), drop repeated darts and keep at most
     // the k smallest (the k-th becomes the cutoff).  All 64 lanes call it.
-    // Up to 512 darts are sorted in registers (below); larger buffers by a
-    // bitonic network over LDS.
+    // Up to 512 darts are sorted in registers (below); fuller buffers (only at
+    // k > 384, where the buffer is a power of two that the padded network
+    // stays within) by a bitonic network over LDS.
     auto bk_compact_lds = [&]() __attribute__((always_inline)) {
         const uint32_t n = bk_count;
         uint32_t N = 64;
