@@ -817,13 +817,14 @@ fast_kernel(const SpecTables* __restrict__ sp, int64_t n_sets, const int64_t* __
                         if (DBG) n_acc += (uint64_t)__popcll(__ballot(acc));
                         if (HK != kHashMix) s = HL(acc, a ^ KS ^ j);
                         if (RT) {
-                            // a dart above its full table's largest is dropped at once;
-                            // the others go to their table's lane through its mailbox,
-                            // one dart per table at a time (tickets in ascending order)
+                            // a dart ranked above its full table's largest is dropped at
+                            // once (one of equal rank goes on: the insertion compares id
+                            // hashes); the others go to their table's lane through its
+                            // mailbox, one dart per table at a time (tickets in ascending order)
                             const uint32_t l = bucket_of(s, (uint32_t)k);
                             const int src = acc ? (int)l : lane;
-                            const uint64_t omr = __shfl(tr[7], src, kWave), oms = __shfl(ts[7], src, kWave);
-                            bool pending = acc && (rb < omr || (rb == omr && s <= oms));
+                            const uint64_t omr = __shfl(tr[7], src, kWave);
+                            bool pending = acc && rb <= omr;
                             if (wave_any(pending)) {
                                 int32_t* const ticket = &at<int32_t>(wb, kOffMark, 0);
                                 if (pending)
